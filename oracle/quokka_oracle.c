@@ -1,0 +1,796 @@
+/*
+ * Plain FP64 CPU oracle of the QUOKKA per-cell update (Wibking & Krumholz 2021,
+ * arXiv:2110.01792).  TEST INFRASTRUCTURE ONLY: the reference that the GPU
+ * library is checked against.  It shares no code with the GPU path.
+ *
+ * Every stage is written as whole-array passes in the order the paper gives:
+ * conserved -> primitive, shock flattening, PPM per direction, Riemann flux
+ * per face, unsplit divergence, SSP-RK2 combination.  No blocking, fusion or
+ * reordering.  Compile with -O2 -ffp-contract=off -fno-fast-math.
+ *
+ * One exact shortcut is taken: an axis with a single interior cell and
+ * non-fixed boundaries has ghost cells that are copies of that cell, so its
+ * two face fluxes are computed from identical inputs and cancel exactly, and
+ * its flattening coefficient is exactly 1.  Such an axis is skipped ("inactive"),
+ * which lets one-dimensional tests run in a 3D box at 1D cost.
+ *
+ * Parity pins are in tests/test_oracle_*.py; see the header of each function for
+ * the passage it follows.
+ */
+#include "quokka_oracle.h"
+
+#include <math.h>
+#include <stddef.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* geometry                                                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int n[3], ng, N[3];
+  size_t vs;          /* elements per variable */
+  ptrdiff_t st[3];    /* element stride per axis */
+  int act[3];         /* axis active (see file header) */
+  int lo[3], hi[3];   /* cell range where primitives are formed */
+} geo;
+
+static geo make_geo(const ob_box* b) {
+  geo g;
+  g.ng = b->ng;
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = b->n[d];
+    g.N[d] = b->n[d] + 2 * b->ng;
+    g.act[d] = !(b->n[d] == 1 && b->bc[d][0] != OB_FIXED && b->bc[d][1] != OB_FIXED);
+    g.lo[d] = g.act[d] ? -b->ng : 0;
+    g.hi[d] = g.act[d] ? b->n[d] + b->ng : b->n[d];
+  }
+  g.st[0] = 1;
+  g.st[1] = g.N[0];
+  g.st[2] = (ptrdiff_t)g.N[0] * g.N[1];
+  g.vs = (size_t)g.N[0] * g.N[1] * g.N[2];
+  return g;
+}
+
+static inline size_t IX(const geo* g, int i, int j, int k) {
+  return ((size_t)(k + g->ng) * g->N[1] + (size_t)(j + g->ng)) * g->N[0] + (size_t)(i + g->ng);
+}
+
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* boundary conditions: periodic wrap, zero-gradient outflow, fixed          */
+/* Filled axis by axis (x, then y over the full x extent, then z over the    */
+/* full x-y extent), which also fills edges and corners.                     */
+/* ------------------------------------------------------------------------ */
+static int src_index(int i, int n, int ng, int bclo, int bchi) {
+  if (i < 0) {
+    if (bclo == OB_PERIODIC) return ((i % n) + n) % n;
+    if (bclo == OB_OUTFLOW) return 0;
+    return i;
+  }
+  if (i >= n) {
+    if (bchi == OB_PERIODIC) return i % n;
+    if (bchi == OB_OUTFLOW) return n - 1;
+    return i;
+  }
+  (void)ng;
+  return i;
+}
+
+void oracle_fill_ghosts(const ob_box* b, double* U, int nvar) {
+  geo g = make_geo(b);
+  const int ng = g.ng;
+  for (int v = 0; v < nvar; ++v) {
+    double* q = U + (size_t)v * g.vs;
+    /* x */
+    for (int k = 0; k < g.n[2]; ++k)
+      for (int j = 0; j < g.n[1]; ++j)
+        for (int i = -ng; i < g.n[0] + ng; ++i) {
+          if (i >= 0 && i < g.n[0]) continue;
+          int s = src_index(i, g.n[0], ng, b->bc[0][0], b->bc[0][1]);
+          if (s != i) q[IX(&g, i, j, k)] = q[IX(&g, s, j, k)];
+        }
+    /* y, over full x extent */
+    for (int k = 0; k < g.n[2]; ++k)
+      for (int j = -ng; j < g.n[1] + ng; ++j) {
+        if (j >= 0 && j < g.n[1]) continue;
+        int s = src_index(j, g.n[1], ng, b->bc[1][0], b->bc[1][1]);
+        if (s == j) continue;
+        for (int i = -ng; i < g.n[0] + ng; ++i) q[IX(&g, i, j, k)] = q[IX(&g, i, s, k)];
+      }
+    /* z, over full x-y extent */
+    for (int k = -ng; k < g.n[2] + ng; ++k) {
+      if (k >= 0 && k < g.n[2]) continue;
+      int s = src_index(k, g.n[2], ng, b->bc[2][0], b->bc[2][1]);
+      if (s == k) continue;
+      for (int j = -ng; j < g.n[1] + ng; ++j)
+        for (int i = -ng; i < g.n[0] + ng; ++i) q[IX(&g, i, j, k)] = q[IX(&g, i, j, s)];
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* PPM reconstruction of one cell (Section 2.2.1, reconstruction paragraphs). */
+/* q[0..4] = cell averages at offsets -2..+2 along the axis.                 */
+/*  1. fourth-order interface values, terms grouped symmetrically about the  */
+/*     interface (sums of the two symmetric pairs first);                    */
+/*  2. clamp each interface value to [min, max] of the cell and its two      */
+/*     neighbours;                                                           */
+/*  3. CW84 extremum test; on an extremum fall back to a linear profile with */
+/*     the monotonized-central slope;                                        */
+/*  4. otherwise CW84 overshoot correction on the affected side.             */
+/* ------------------------------------------------------------------------ */
+static void ppm(double qm2, double qm1, double q0, double qp1, double qp2, double* aL, double* aR) {
+  double fl = (7.0 / 12.0) * (qm1 + q0) - (1.0 / 12.0) * (qm2 + qp1);
+  double fr = (7.0 / 12.0) * (q0 + qp1) - (1.0 / 12.0) * (qm1 + qp2);
+  double lo = fmin(qm1, fmin(q0, qp1));
+  double hi = fmax(qm1, fmax(q0, qp1));
+  fl = fmin(fmax(fl, lo), hi);
+  fr = fmin(fmax(fr, lo), hi);
+  if ((fr - q0) * (q0 - fl) <= 0.0) {
+    double dl = q0 - qm1, dr = qp1 - q0, dc = qp1 - qm1;
+    double s = 0.0;
+    if (dr * dl > 0.0) {
+      s = fmin(fmin(2.0 * fabs(dr), 2.0 * fabs(dl)), 0.5 * fabs(dc));
+      if (dc < 0.0) s = -s;
+    }
+    fl = q0 - 0.5 * s;
+    fr = q0 + 0.5 * s;
+  } else {
+    double del = fr - fl;
+    double a6 = 6.0 * (q0 - 0.5 * (fl + fr));
+    if (del * a6 > del * del)
+      fl = 3.0 * q0 - 2.0 * fr;
+    else if (del * a6 < -(del * del))
+      fr = 3.0 * q0 - 2.0 * fl;
+  }
+  *aL = fl;
+  *aR = fr;
+}
+
+void oracle_ppm_cell(const double q[5], double out[2]) { ppm(q[0], q[1], q[2], q[3], q[4], &out[0], &out[1]); }
+
+/* ------------------------------------------------------------------------ */
+/* HLLC flux with PVRS wave-speed estimates (Section 2.2.1, Riemann solver   */
+/* paragraph; Toro 2013 ch. 10).  States are primitive and rotated so that   */
+/* index 1 is the face-normal velocity.  The star state is grouped so that a */
+/* stationary contact is preserved exactly, and the two tangential speeds    */
+/* enter the kinetic energy as one symmetric pair, so relabelling x and y    */
+/* changes no bit of any flux.                                               */
+/* ------------------------------------------------------------------------ */
+void oracle_hllc(const double WL[5], const double WR[5], double g, double F[5]) {
+  const double rL = WL[0], uL = WL[1], vL = WL[2], wL = WL[3], pL = WL[4];
+  const double rR = WR[0], uR = WR[1], vR = WR[2], wR = WR[3], pR = WR[4];
+  const double cL = sqrt(g * pL / rL);
+  const double cR = sqrt(g * pR / rR);
+  const double EL = pL / (g - 1.0) + 0.5 * rL * (uL * uL + (vL * vL + wL * wL));
+  const double ER = pR / (g - 1.0) + 0.5 * rR * (uR * uR + (vR * vR + wR * wR));
+  const double rbar = 0.5 * (rL + rR);
+  const double cbar = 0.5 * (cL + cR);
+  const double pstar = fmax(0.0, 0.5 * (pL + pR) - 0.5 * (uR - uL) * rbar * cbar);
+  const double qL = (pstar <= pL) ? 1.0 : sqrt(1.0 + ((g + 1.0) / (2.0 * g)) * (pstar / pL - 1.0));
+  const double qR = (pstar <= pR) ? 1.0 : sqrt(1.0 + ((g + 1.0) / (2.0 * g)) * (pstar / pR - 1.0));
+  const double SL = uL - cL * qL;
+  const double SR = uR + cR * qR;
+  const double Ss = ((pR - pL) + rL * uL * (SL - uL) - rR * uR * (SR - uR)) /
+                    (rL * (SL - uL) - rR * (SR - uR));
+
+  const double FL[5] = {rL * uL, rL * uL * uL + pL, rL * uL * vL, rL * uL * wL, uL * (EL + pL)};
+  const double FR[5] = {rR * uR, rR * uR * uR + pR, rR * uR * vR, rR * uR * wR, uR * (ER + pR)};
+
+  if (0.0 <= SL) {
+    for (int n = 0; n < 5; ++n) F[n] = FL[n];
+  } else if (0.0 <= Ss) {
+    const double UL[5] = {rL, rL * uL, rL * vL, rL * wL, EL};
+    const double ph = (SL - uL) / (SL - Ss);
+    const double Us[5] = {ph * rL, ph * (rL * Ss), ph * (rL * vL), ph * (rL * wL),
+                          ph * (EL + (Ss - uL) * (rL * Ss + pL / (SL - uL)))};
+    for (int n = 0; n < 5; ++n) F[n] = FL[n] + SL * (Us[n] - UL[n]);
+  } else if (0.0 < SR) {
+    const double UR[5] = {rR, rR * uR, rR * vR, rR * wR, ER};
+    const double ph = (SR - uR) / (SR - Ss);
+    const double Us[5] = {ph * rR, ph * (rR * Ss), ph * (rR * vR), ph * (rR * wR),
+                          ph * (ER + (Ss - uR) * (rR * Ss + pR / (SR - uR)))};
+    for (int n = 0; n < 5; ++n) F[n] = FR[n] + SR * (Us[n] - UR[n]);
+  } else {
+    for (int n = 0; n < 5; ++n) F[n] = FR[n];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hydrodynamic right-hand side L(U) (Section 2.2.1).                        */
+/* ------------------------------------------------------------------------ */
+static void to_prim(const double* U, size_t vs, size_t o, double g, double W[5]) {
+  const double rho = U[o], mx = U[vs + o], my = U[2 * vs + o], mz = U[3 * vs + o], E = U[4 * vs + o];
+  const double ek = 0.5 * ((mx * mx + my * my) + mz * mz) / rho;
+  W[0] = rho;
+  W[1] = mx / rho;
+  W[2] = my / rho;
+  W[3] = mz / rho;
+  W[4] = (g - 1.0) * (E - ek);
+}
+
+/* Flattening coefficient of one cell along one axis before the neighbour
+ * minimum (Miller & Colella 2002 generalisation of CW84, constants of CW84). */
+static double chi_tilde(const double* P, const double* u, size_t o, ptrdiff_t s) {
+  const double dp1 = P[o + s] - P[o - s];
+  const double dp2 = P[o + 2 * s] - P[o - 2 * s];
+  const double du = u[o + s] - u[o - s];
+  const int shock = (fabs(dp1) > 0.33 * fmin(P[o + s], P[o - s])) && (du < 0.0);
+  if (!shock) return 1.0;
+  const double z = fabs(dp1) / fmax(fabs(dp2), 1e-300);
+  return fmin(1.0, fmax(0.0, 1.0 - (z - 0.75) / (0.85 - 0.75)));
+}
+
+#define LOOP3(K0, K1, J0, J1, I0, I1)                               \
+  _Pragma("omp parallel for collapse(2) schedule(static)")          \
+  for (int k = (K0); k < (K1); ++k)                                 \
+    for (int j = (J0); j < (J1); ++j)                               \
+      for (int i = (I0); i < (I1); ++i)
+
+void oracle_hydro_rhs(const ob_box* b, const double* U, double gam, double* L, ob_stats* st) {
+  geo g = make_geo(b);
+  const size_t vs = g.vs;
+  double* W = (double*)malloc(5 * vs * sizeof(double));
+  double* cht = (double*)malloc(3 * vs * sizeof(double));
+  double* chi = (double*)malloc(vs * sizeof(double));
+  double* aL = (double*)malloc(5 * vs * sizeof(double));
+  double* aR = (double*)malloc(5 * vs * sizeof(double));
+  double* Fd = (double*)malloc(3 * 5 * vs * sizeof(double));
+  int64_t neg = 0;
+
+  /* 1. conserved -> primitive */
+  LOOP3(g.lo[2], g.hi[2], g.lo[1], g.hi[1], g.lo[0], g.hi[0]) {
+    const size_t o = IX(&g, i, j, k);
+    double w[5];
+    to_prim(U, vs, o, gam, w);
+    for (int v = 0; v < 5; ++v) W[v * vs + o] = w[v];
+  }
+  for (int k = 0; k < g.n[2]; ++k)
+    for (int j = 0; j < g.n[1]; ++j)
+      for (int i = 0; i < g.n[0]; ++i) {
+        const size_t o = IX(&g, i, j, k);
+        if (!(W[o] > 0.0) || !(W[4 * vs + o] > 0.0)) ++neg;
+      }
+
+  /* 2. shock flattening: per-axis coefficient, neighbour minimum toward the
+   *    higher pressure, then the minimum over axes. */
+  const double* P = W + 4 * vs;
+  for (int d = 0; d < 3; ++d) {
+    double* c = cht + d * vs;
+    if (!g.act[d]) continue;
+    int lo[3] = {g.lo[0], g.lo[1], g.lo[2]}, hi[3] = {g.hi[0], g.hi[1], g.hi[2]};
+    lo[d] += 2;
+    hi[d] -= 2;
+    const double* u = W + (1 + d) * vs;
+    LOOP3(lo[2], hi[2], lo[1], hi[1], lo[0], hi[0]) {
+      const size_t o = IX(&g, i, j, k);
+      c[o] = chi_tilde(P, u, o, g.st[d]);
+    }
+  }
+  {
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = g.act[d] ? -1 : 0;
+      hi[d] = g.act[d] ? g.n[d] + 1 : g.n[d];
+    }
+    LOOP3(lo[2], hi[2], lo[1], hi[1], lo[0], hi[0]) {
+      const size_t o = IX(&g, i, j, k);
+      double x = 1.0;
+      for (int d = 0; d < 3; ++d) {
+        if (!g.act[d]) continue;
+        const ptrdiff_t s = g.st[d];
+        const double dp1 = P[o + s] - P[o - s];
+        const ptrdiff_t sh = (dp1 > 0.0) ? s : -s;
+        const double* c = cht + d * vs;
+        x = fmin(x, fmin(c[o], c[o + sh]));
+      }
+      chi[o] = x;
+    }
+  }
+
+  /* 3-4. per axis: PPM of (rho, vx, vy, vz, P) with flattening, then HLLC at
+   *      every face.  Face c-1/2 is stored at cell c. */
+  for (int d = 0; d < 3; ++d) {
+    double* F = Fd + (size_t)d * 5 * vs;
+    if (!g.act[d]) continue;
+    const ptrdiff_t s = g.st[d];
+    int lo[3] = {0, 0, 0}, hi[3] = {g.n[0], g.n[1], g.n[2]};
+    lo[d] = -1;
+    hi[d] = g.n[d] + 1;
+    LOOP3(lo[2], hi[2], lo[1], hi[1], lo[0], hi[0]) {
+      const size_t o = IX(&g, i, j, k);
+      const double x = chi[o];
+      for (int v = 0; v < 5; ++v) {
+        const double* q = W + v * vs;
+        double l, r;
+        ppm(q[o - 2 * s], q[o - s], q[o], q[o + s], q[o + 2 * s], &l, &r);
+        aL[v * vs + o] = x * l + (1.0 - x) * q[o];
+        aR[v * vs + o] = x * r + (1.0 - x) * q[o];
+      }
+    }
+    int lo2[3] = {0, 0, 0}, hi2[3] = {g.n[0], g.n[1], g.n[2]};
+    hi2[d] = g.n[d] + 1;
+    /* rotation: normal velocity first, then the two tangential ones */
+    const int t1 = (d == 0) ? 2 : 1;
+    const int t2 = (d == 2) ? 2 : 3;
+    const int nv = 1 + d;
+    LOOP3(lo2[2], hi2[2], lo2[1], hi2[1], lo2[0], hi2[0]) {
+      const size_t o = IX(&g, i, j, k);
+      const size_t ol = o - s;
+      const double WLr[5] = {aR[ol], aR[nv * vs + ol], aR[t1 * vs + ol], aR[t2 * vs + ol], aR[4 * vs + ol]};
+      const double WRr[5] = {aL[o], aL[nv * vs + o], aL[t1 * vs + o], aL[t2 * vs + o], aL[4 * vs + o]};
+      double f[5];
+      oracle_hllc(WLr, WRr, gam, f);
+      F[0 * vs + o] = f[0];
+      F[nv * vs + o] = f[1];
+      F[t1 * vs + o] = f[2];
+      F[t2 * vs + o] = f[3];
+      F[4 * vs + o] = f[4];
+    }
+  }
+
+  /* 5. unsplit divergence, x and y first so that the two are symmetric */
+  LOOP3(0, g.n[2], 0, g.n[1], 0, g.n[0]) {
+    const size_t o = IX(&g, i, j, k);
+    for (int v = 0; v < 5; ++v) {
+      double t[3];
+      for (int d = 0; d < 3; ++d) {
+        if (!g.act[d]) {
+          t[d] = 0.0;
+          continue;
+        }
+        const double* F = Fd + (size_t)d * 5 * vs + v * vs;
+        t[d] = (F[o + g.st[d]] - F[o]) / b->dx[d];
+      }
+      L[v * vs + o] = -((t[0] + t[1]) + t[2]);
+    }
+  }
+  if (st) st->neg_cells += neg;
+  free(W);
+  free(cht);
+  free(chi);
+  free(aL);
+  free(aR);
+  free(Fd);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Time step (Section 2.2.1, eqs. for |lambda| and Delta t): the CFL number  */
+/* multiplies min(dx) / max over interior cells of (|v| + c_s).              */
+/* ------------------------------------------------------------------------ */
+double oracle_hydro_max_signal(const ob_box* b, const double* U, double gam) {
+  geo g = make_geo(b);
+  double smax = 0.0;
+#pragma omp parallel for collapse(2) reduction(max : smax)
+  for (int k = 0; k < g.n[2]; ++k)
+    for (int j = 0; j < g.n[1]; ++j)
+      for (int i = 0; i < g.n[0]; ++i) {
+        double w[5];
+        to_prim(U, g.vs, IX(&g, i, j, k), gam, w);
+        const double vv = sqrt((w[1] * w[1] + w[2] * w[2]) + w[3] * w[3]);
+        const double cs = sqrt(gam * w[4] / w[0]);
+        const double s = vv + cs;
+        if (s > smax) smax = s;
+      }
+  return smax;
+}
+
+static double dx_min(const ob_box* b) {
+  double m = b->dx[0];
+  for (int d = 1; d < 3; ++d)
+    if (b->dx[d] < m) m = b->dx[d];
+  return m;
+}
+
+/* One SSP-RK2 step (Shu & Osher 1988): U1 = U + dt L(U);
+ * U <- 0.5 U + 0.5 (U1 + dt L(U1)); ghosts refilled after each stage. */
+static void rk2_interior(const geo* g, int nvar, double* Un, const double* U1, const double* L1, double dt) {
+  LOOP3(0, g->n[2], 0, g->n[1], 0, g->n[0]) {
+    const size_t o = IX(g, i, j, k);
+    for (int v = 0; v < nvar; ++v) {
+      const size_t p = v * g->vs + o;
+      Un[p] = 0.5 * Un[p] + 0.5 * (U1[p] + dt * L1[p]);
+    }
+  }
+}
+
+static void euler_interior(const geo* g, int nvar, const double* Un, double* U1, const double* L, double dt) {
+  LOOP3(0, g->n[2], 0, g->n[1], 0, g->n[0]) {
+    const size_t o = IX(g, i, j, k);
+    for (int v = 0; v < nvar; ++v) {
+      const size_t p = v * g->vs + o;
+      U1[p] = Un[p] + dt * L[p];
+    }
+  }
+}
+
+static void hydro_rk2(const ob_box* b, double* U, double gam, double dt, ob_stats* st) {
+  geo g = make_geo(b);
+  const size_t nb = 5 * g.vs * sizeof(double);
+  double* U1 = (double*)malloc(nb);
+  double* Lb = (double*)calloc(5 * g.vs, sizeof(double));
+  memcpy(U1, U, nb); /* fixed ghosts of the stage state equal those of U */
+  oracle_hydro_rhs(b, U, gam, Lb, st);
+  euler_interior(&g, 5, U, U1, Lb, dt);
+  oracle_fill_ghosts(b, U1, 5);
+  oracle_hydro_rhs(b, U1, gam, Lb, st);
+  rk2_interior(&g, 5, U, U1, Lb, dt);
+  oracle_fill_ghosts(b, U, 5);
+  free(U1);
+  free(Lb);
+}
+
+void oracle_hydro_step(const ob_box* b, double* U, double gam, double cfl, double dt_in, ob_stats* st) {
+  oracle_fill_ghosts(b, U, 5);
+  double dt = dt_in;
+  if (!(dt > 0.0)) dt = cfl * dx_min(b) / oracle_hydro_max_signal(b, U, gam);
+  hydro_rk2(b, U, gam, dt, st);
+  if (st) {
+    st->dt = dt;
+    st->nsub = 0;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Radiation closure (Section 2.2.2, eq. M1_closure and the Levermore        */
+/* Eddington factor).  fhat = |F|/(cE) is capped at 1 for the closure only. */
+/* With F = 0 the direction-dependent term is dropped.                       */
+/* ------------------------------------------------------------------------ */
+double oracle_closure_chi(double f, int closure) {
+  if (closure == 1) return 1.0 / 3.0;
+  return (3.0 + 4.0 * f * f) / (5.0 + 2.0 * sqrt(4.0 - 3.0 * f * f));
+}
+
+void oracle_closure_pressure(double E, const double F[3], double c, int closure, double P[9]) {
+  const double Fn = sqrt((F[0] * F[0] + F[1] * F[1]) + F[2] * F[2]);
+  const double fh = fmin(Fn / (c * E), 1.0);
+  const double chi = oracle_closure_chi(fh, closure);
+  const double a = 0.5 * (1.0 - chi);
+  const double bb = 0.5 * (3.0 * chi - 1.0);
+  double n[3] = {0.0, 0.0, 0.0};
+  if (Fn > 0.0)
+    for (int i = 0; i < 3; ++i) n[i] = F[i] / Fn;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const double iso = (i == j) ? a : 0.0;
+      P[3 * i + j] = (Fn > 0.0) ? E * (iso + bb * n[i] * n[j]) : E * iso;
+    }
+}
+
+/* HLL flux of (E_r, F) along axis dir under the reduced speed of light
+ * (eqs. rad_energy, rad_flux): physical flux ((chat/c) F_d, c chat P_d*);
+ * both wave speeds are +-chat * sqrt(P_dd / E), the larger of the two face
+ * states, with the Eddington tensor frozen (Balsara 1999).  eps scales the
+ * upwind dissipation (optical-depth correction). */
+void oracle_hll_rad(double EL, const double FL[3], double ER, const double FR[3], int dir, const ob_rad* p,
+                    double eps, double flux[4]) {
+  double PL[9], PR[9];
+  oracle_closure_pressure(EL, FL, p->c, p->closure, PL);
+  oracle_closure_pressure(ER, FR, p->c, p->closure, PR);
+  const double sL = sqrt(PL[4 * dir] / EL);
+  const double sR = sqrt(PR[4 * dir] / ER);
+  const double S = p->chat * fmax(sL, sR);
+  const double cc = p->c * p->chat;
+  const double ratio = p->chat / p->c;
+  const double phL[4] = {ratio * FL[dir], cc * PL[3 * dir + 0], cc * PL[3 * dir + 1], cc * PL[3 * dir + 2]};
+  const double phR[4] = {ratio * FR[dir], cc * PR[3 * dir + 0], cc * PR[3 * dir + 1], cc * PR[3 * dir + 2]};
+  const double UL[4] = {EL, FL[0], FL[1], FL[2]};
+  const double UR[4] = {ER, FR[0], FR[1], FR[2]};
+  for (int n = 0; n < 4; ++n) flux[n] = 0.5 * (phL[n] + phR[n]) - 0.5 * eps * S * (UR[n] - UL[n]);
+}
+
+/* Radiation transport right-hand side (Section 2.2.2): PPM (no flattening)
+ * of E_r and the reduced flux f = F/(c E_r); per-face first-order fallback
+ * when either reconstructed |f| exceeds 1; closure; HLL; unsplit divergence. */
+void oracle_rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const ob_rad* p, double* L, ob_stats* st) {
+  geo g = make_geo(b);
+  const size_t vs = g.vs;
+  double* Q = (double*)malloc(4 * vs * sizeof(double));
+  double* aL = (double*)malloc(4 * vs * sizeof(double));
+  double* aR = (double*)malloc(4 * vs * sizeof(double));
+  double* Fd = (double*)malloc(3 * 4 * vs * sizeof(double));
+  const double c = p->c;
+  int64_t neg = 0;
+
+  LOOP3(g.lo[2], g.hi[2], g.lo[1], g.hi[1], g.lo[0], g.hi[0]) {
+    const size_t o = IX(&g, i, j, k);
+    const double E = Ur[o];
+    Q[o] = E;
+    for (int d = 0; d < 3; ++d) Q[(1 + d) * vs + o] = Ur[(1 + d) * vs + o] / (c * E);
+  }
+  for (int k = 0; k < g.n[2]; ++k)
+    for (int j = 0; j < g.n[1]; ++j)
+      for (int i = 0; i < g.n[0]; ++i)
+        if (!(Ur[IX(&g, i, j, k)] > 0.0)) ++neg;
+
+  for (int d = 0; d < 3; ++d) {
+    double* F = Fd + (size_t)d * 4 * vs;
+    if (!g.act[d]) continue;
+    const ptrdiff_t s = g.st[d];
+    int lo[3] = {0, 0, 0}, hi[3] = {g.n[0], g.n[1], g.n[2]};
+    lo[d] = -1;
+    hi[d] = g.n[d] + 1;
+    LOOP3(lo[2], hi[2], lo[1], hi[1], lo[0], hi[0]) {
+      const size_t o = IX(&g, i, j, k);
+      for (int v = 0; v < 4; ++v) {
+        const double* q = Q + v * vs;
+        ppm(q[o - 2 * s], q[o - s], q[o], q[o + s], q[o + 2 * s], &aL[v * vs + o], &aR[v * vs + o]);
+      }
+    }
+    int lo2[3] = {0, 0, 0}, hi2[3] = {g.n[0], g.n[1], g.n[2]};
+    hi2[d] = g.n[d] + 1;
+    LOOP3(lo2[2], hi2[2], lo2[1], hi2[1], lo2[0], hi2[0]) {
+      const size_t o = IX(&g, i, j, k);
+      const size_t ol = o - s;
+      double EL = aR[ol], ER = aL[o];
+      const double fL[3] = {aR[vs + ol], aR[2 * vs + ol], aR[3 * vs + ol]};
+      const double fR[3] = {aL[vs + o], aL[2 * vs + o], aL[3 * vs + o]};
+      const double nL = sqrt((fL[0] * fL[0] + fL[1] * fL[1]) + fL[2] * fL[2]);
+      const double nR = sqrt((fR[0] * fR[0] + fR[1] * fR[1]) + fR[2] * fR[2]);
+      double FLv[3], FRv[3];
+      const int fallback = (nL > 1.0) || (nR > 1.0);
+      if (fallback) {
+        EL = Ur[ol];
+        ER = Ur[o];
+        for (int m = 0; m < 3; ++m) {
+          FLv[m] = Ur[(1 + m) * vs + ol];
+          FRv[m] = Ur[(1 + m) * vs + o];
+        }
+      } else {
+        for (int m = 0; m < 3; ++m) {
+          FLv[m] = c * EL * fL[m];
+          FRv[m] = c * ER * fR[m];
+        }
+      }
+      double eps = 1.0;
+      if (p->tau_correction && !fallback) {
+        const double tau = b->dx[d] * p->kappa_R * (0.5 * (Ug[ol] + Ug[o]));
+        eps = fmin(1.0, 1.0 / tau);
+      }
+      double f[4];
+      oracle_hll_rad(EL, FLv, ER, FRv, d, p, eps, f);
+      for (int v = 0; v < 4; ++v) F[v * vs + o] = f[v];
+    }
+  }
+
+  LOOP3(0, g.n[2], 0, g.n[1], 0, g.n[0]) {
+    const size_t o = IX(&g, i, j, k);
+    for (int v = 0; v < 4; ++v) {
+      double t[3];
+      for (int d = 0; d < 3; ++d) {
+        if (!g.act[d]) {
+          t[d] = 0.0;
+          continue;
+        }
+        const double* F = Fd + (size_t)d * 4 * vs + v * vs;
+        t[d] = (F[o + g.st[d]] - F[o]) / b->dx[d];
+      }
+      L[v * vs + o] = -((t[0] + t[1]) + t[2]);
+    }
+  }
+  if (st) st->neg_cells += neg;
+  free(Q);
+  free(aL);
+  free(aR);
+  free(Fd);
+}
+
+void oracle_rad_transport_substep(const ob_box* b, double* Ur, const double* Ug, const ob_rad* p, double dt,
+                                  ob_stats* st) {
+  geo g = make_geo(b);
+  const size_t nb = 4 * g.vs * sizeof(double);
+  double* U1 = (double*)malloc(nb);
+  double* Lb = (double*)calloc(4 * g.vs, sizeof(double));
+  memcpy(U1, Ur, nb);
+  oracle_rad_rhs(b, Ur, Ug, p, Lb, st);
+  euler_interior(&g, 4, Ur, U1, Lb, dt);
+  oracle_fill_ghosts(b, U1, 4);
+  oracle_rad_rhs(b, U1, Ug, p, Lb, st);
+  rk2_interior(&g, 4, Ur, U1, Lb, dt);
+  oracle_fill_ghosts(b, Ur, 4);
+  free(U1);
+  free(Lb);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Matter-radiation coupling of one cell (Section 2.2.3).                    */
+/*  (a) backward-Euler energy exchange solved by Newton-Raphson on (E_g,E_r) */
+/*      with R = dt rho kappa_P chat (a_r T^4 - E_r), the Jacobian and the   */
+/*      eta elimination of the paper, residuals checked before each update;  */
+/*  (b) backward-Euler flux source F <- F / (1 + rho kappa_F chat dt), and   */
+/*      the equal and opposite change of gas momentum, dm = -dF/(chat c);    */
+/*  (c) work term from the change of gas kinetic energy.                     */
+/* gas = (rho, mx, my, mz, E), rad = (E_r, Fx, Fy, Fz).  Returns 0 on        */
+/* convergence, 1 if the iteration cap was reached.                          */
+/* ------------------------------------------------------------------------ */
+int oracle_exchange_cell(const ob_rad* p, double dt, double* gas, double* rad, int* iters) {
+  const double rho = gas[0];
+  const double c = p->c, ch = p->chat;
+  const double Ek0 = 0.5 * ((gas[1] * gas[1] + gas[2] * gas[2]) + gas[3] * gas[3]) / rho;
+  const double Eg0 = gas[4] - Ek0;
+  const double Er0 = rad[0];
+  const double Ssrc = 0.0;
+  const double Etot = Eg0 + (c / ch) * (Er0 + Ssrc);
+  double Eg = Eg0, Er = Er0;
+  int it, ok = 0;
+  for (it = 0; it < p->newton_max_iter; ++it) {
+    double T4, dTdE_T3; /* a_r T^4 and 4 a_r T^3 / C_v */
+    if (p->eos == 1) {
+      T4 = 4.0 * Eg / p->alpha_cv;
+      const double T = sqrt(sqrt(T4));
+      const double Cv = p->alpha_cv * T * T * T;
+      dTdE_T3 = 4.0 * p->a_r * T * T * T / Cv;
+    } else {
+      const double T = Eg * (p->gamma - 1.0) / rho;
+      const double Cv = rho / (p->gamma - 1.0);
+      T4 = (T * T) * (T * T);
+      dTdE_T3 = 4.0 * p->a_r * T * T * T / Cv;
+    }
+    const double R = dt * rho * p->kappa_P * ch * (p->a_r * T4 - Er);
+    const double FG = (Eg - Eg0) + (c / ch) * R;
+    const double FR = (Er - Er0) - (R + Ssrc);
+    if (fabs(FG / Etot) < p->newton_tol && fabs((c / ch) * FR / Etot) < p->newton_tol) {
+      ok = 1;
+      break;
+    }
+    const double dRdEg = dt * rho * p->kappa_P * ch * dTdE_T3;
+    const double dFG_dEg = 1.0 + (c / ch) * dRdEg;
+    const double dFG_dEr = -c * dt * rho * p->kappa_P;
+    const double dFR_dEg = -dRdEg;
+    const double dFR_dEr = 1.0 + ch * dt * rho * p->kappa_P;
+    const double eta = -dFR_dEg / dFG_dEg;
+    const double dEr = -(FR + eta * FG) / (dFR_dEr + eta * dFG_dEr);
+    const double dEg = -(FG + dEr * dFG_dEr) / dFG_dEg;
+    Eg += dEg;
+    Er += dEr;
+  }
+  if (iters) *iters = it;
+
+  /* (b) flux and momentum */
+  const double fac = 1.0 + rho * p->kappa_R * ch * dt;
+  double m[3];
+  for (int d = 0; d < 3; ++d) {
+    const double F0 = rad[1 + d];
+    const double F1 = F0 / fac;
+    m[d] = gas[1 + d] - (F1 - F0) / (ch * c);
+    rad[1 + d] = F1;
+  }
+  /* (c) work */
+  const double Ek1 = 0.5 * ((m[0] * m[0] + m[1] * m[1]) + m[2] * m[2]) / rho;
+  const double dEk = Ek1 - Ek0;
+  gas[1] = m[0];
+  gas[2] = m[1];
+  gas[3] = m[2];
+  gas[4] = Eg + (Ek0 + dEk);
+  rad[0] = Er - (ch / c) * dEk;
+  return ok ? 0 : 1;
+}
+
+void oracle_exchange_all(const ob_box* b, double* Ug, double* Ur, const ob_rad* p, double dt, ob_stats* st) {
+  geo g = make_geo(b);
+  int64_t fails = 0, itmax = 0;
+#pragma omp parallel for collapse(2) reduction(+ : fails) reduction(max : itmax)
+  for (int k = 0; k < g.n[2]; ++k)
+    for (int j = 0; j < g.n[1]; ++j)
+      for (int i = 0; i < g.n[0]; ++i) {
+        const size_t o = IX(&g, i, j, k);
+        double gas[5], rad[4];
+        for (int v = 0; v < 5; ++v) gas[v] = Ug[v * g.vs + o];
+        for (int v = 0; v < 4; ++v) rad[v] = Ur[v * g.vs + o];
+        int it = 0;
+        fails += oracle_exchange_cell(p, dt, gas, rad, &it);
+        if (it > itmax) itmax = it;
+        for (int v = 0; v < 5; ++v) Ug[v * g.vs + o] = gas[v];
+        for (int v = 0; v < 4; ++v) Ur[v * g.vs + o] = rad[v];
+      }
+  if (st) {
+    st->newton_fail += fails;
+    if (itmax > st->newton_iter_max) st->newton_iter_max = itmax;
+  }
+}
+
+/* Repeated exchange on one cell with no transport (the energy-exchange test
+ * of Section 3.2).  Writes a_r-free T^4 every `every` steps into T4_out (if
+ * given) and returns the final T^4. */
+double oracle_exchange_series(const ob_rad* p, double dt, int64_t nsteps, double* gas, double* rad, double* T4_out,
+                              int64_t every) {
+  double T4 = 0.0;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    int it;
+    oracle_exchange_cell(p, dt, gas, rad, &it);
+    const double Eg = gas[4] - 0.5 * ((gas[1] * gas[1] + gas[2] * gas[2]) + gas[3] * gas[3]) / gas[0];
+    if (p->eos == 1) {
+      T4 = 4.0 * Eg / p->alpha_cv;
+    } else {
+      const double T = Eg * (p->gamma - 1.0) / gas[0];
+      T4 = (T * T) * (T * T);
+    }
+    if (T4_out && every > 0 && ((s + 1) % every) == 0) T4_out[(s + 1) / every - 1] = T4;
+  }
+  return T4;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Radiation-hydrodynamics step (Section 2.2, operator split; Section 2.2.4  */
+/* substep cap).  Hydro dt from the gas CFL condition; radiation substep     */
+/* limit CFL*min(dx)/chat; N = ceil(dt_h/dt_r) capped at N_sub,max, shrinking */
+/* dt_h to N dt_r when capped; then hydro RK2 and N x (radiation RK2 +       */
+/* coupling) with dt_h / N.                                                  */
+/* ------------------------------------------------------------------------ */
+static int nsub_for(double* dt_h, double dt_r, int nsub_max) {
+  double r = ceil(*dt_h / dt_r);
+  int N = (r < 1.0) ? 1 : (r > (double)nsub_max ? nsub_max + 1 : (int)r);
+  if (N > nsub_max) {
+    N = nsub_max;
+    *dt_h = N * dt_r;
+  }
+  return N;
+}
+
+void oracle_rhd_step(const ob_box* b, double* Ug, double* Ur, const ob_rad* p, double dt_in, ob_stats* st) {
+  oracle_fill_ghosts(b, Ug, 5);
+  oracle_fill_ghosts(b, Ur, 4);
+  double dt_h = dt_in;
+  if (!(dt_h > 0.0)) dt_h = p->cfl * dx_min(b) / oracle_hydro_max_signal(b, Ug, p->gamma);
+  const double dt_r = p->cfl * dx_min(b) / p->chat;
+  const int N = nsub_for(&dt_h, dt_r, p->nsub_max);
+  const double dts = dt_h / N;
+  hydro_rk2(b, Ug, p->gamma, dt_h, st);
+  for (int s = 0; s < N; ++s) {
+    oracle_rad_transport_substep(b, Ur, Ug, p, dts, st);
+    oracle_exchange_all(b, Ug, Ur, p, dts, st);
+    oracle_fill_ghosts(b, Ug, 5);
+    oracle_fill_ghosts(b, Ur, 4);
+  }
+  if (st) {
+    st->dt = dt_h;
+    st->nsub = N;
+  }
+}
+
+/* One level step over independent boxes whose ghost cells are held at their
+ * given values: one level-wide hydro dt (minimum over boxes), one substep
+ * count from chat, every box advanced with them.  Ur[i] == NULL marks a
+ * hydro-only box. */
+void oracle_batch_step(int32_t nbox, const ob_box* boxes, double* const* Ug, double* const* Ur, double gamma_h,
+                       double cfl, const ob_rad* p, ob_stats* st) {
+  double dt_h = INFINITY, dxm = INFINITY;
+  int any_rad = 0;
+  for (int i = 0; i < nbox; ++i) {
+    const double gam = Ur[i] ? p->gamma : gamma_h;
+    const double dt = cfl * dx_min(&boxes[i]) / oracle_hydro_max_signal(&boxes[i], Ug[i], gam);
+    if (dt < dt_h) dt_h = dt;
+    if (Ur[i]) {
+      any_rad = 1;
+      if (dx_min(&boxes[i]) < dxm) dxm = dx_min(&boxes[i]);
+    }
+  }
+  int N = 0;
+  if (any_rad) N = nsub_for(&dt_h, cfl * dxm / p->chat, p->nsub_max);
+  for (int i = 0; i < nbox; ++i) {
+    const double gam = Ur[i] ? p->gamma : gamma_h;
+    hydro_rk2(&boxes[i], Ug[i], gam, dt_h, st);
+    if (!Ur[i]) continue;
+    for (int s = 0; s < N; ++s) {
+      oracle_rad_transport_substep(&boxes[i], Ur[i], Ug[i], p, dt_h / N, st);
+      oracle_exchange_all(&boxes[i], Ug[i], Ur[i], p, dt_h / N, st);
+    }
+  }
+  if (st) {
+    st->dt = dt_h;
+    st->nsub = N;
+  }
+}

@@ -1,0 +1,72 @@
+/*
+ * Plain FP64 CPU oracle for the per-cell radiation-hydrodynamics update of
+ * Wibking & Krumholz (2021), "QUOKKA: a code for two-moment AMR radiation
+ * hydrodynamics on GPUs" (arXiv:2110.01792).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously-correct
+ * reference that the GPU path is checked against.  Only the test suite, the
+ * smoke check and the benchmark's CPU-baseline leg may load it.  It shares no
+ * code, header, constant or helper with the GPU library.
+ *
+ * Array layout used by every entry point: one contiguous float64 array per
+ * state, shape (nvar, nz+2ng, ny+2ng, nx+2ng), x fastest.  Gas state has
+ * nvar = 5 (rho, rho*vx, rho*vy, rho*vz, E); radiation state has nvar = 4
+ * (E_r, F_x, F_y, F_z).
+ */
+#ifndef QUOKKA_ORACLE_H
+#define QUOKKA_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OB_PERIODIC = 0, OB_OUTFLOW = 1, OB_FIXED = 2 };
+
+typedef struct {
+  int32_t n[3];      /* interior cells per axis */
+  int32_t ng;        /* ghost layers (>= 4) */
+  double dx[3];      /* cell widths */
+  int32_t bc[3][2];  /* per axis, lo/hi boundary kind */
+} ob_box;
+
+typedef struct {
+  double c, chat, a_r, kappa_P, kappa_R, gamma, alpha_cv, cfl, newton_tol;
+  int32_t newton_max_iter, nsub_max, closure, tau_correction, eos;
+} ob_rad;   /* closure: 0 Levermore, 1 Eddington.  eos: 0 ideal (P = rho T),
+               1 E_g = alpha T^4 / 4. */
+
+/* Result counters returned by the step drivers. */
+typedef struct {
+  int64_t neg_cells;      /* cells with rho<=0, P<=0 or E_r<=0 met */
+  int64_t newton_fail;    /* cells whose exchange solve hit the iteration cap */
+  int64_t newton_iter_max;/* largest iteration count of any cell */
+  int32_t nsub;           /* radiation substeps taken */
+  double dt;              /* hydro step actually taken */
+} ob_stats;
+
+void   oracle_fill_ghosts(const ob_box* b, double* U, int nvar);
+double oracle_hydro_max_signal(const ob_box* b, const double* U, double gamma);
+void   oracle_hydro_rhs(const ob_box* b, const double* U, double gamma, double* L, ob_stats* st);
+void   oracle_hydro_step(const ob_box* b, double* U, double gamma, double cfl, double dt_in, ob_stats* st);
+void   oracle_rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const ob_rad* p, double* L, ob_stats* st);
+void   oracle_rad_transport_substep(const ob_box* b, double* Ur, const double* Ug, const ob_rad* p, double dt, ob_stats* st);
+int    oracle_exchange_cell(const ob_rad* p, double dt, double* rho_m_E /*5*/, double* Er_F /*4*/, int* iters);
+void   oracle_exchange_all(const ob_box* b, double* Ug, double* Ur, const ob_rad* p, double dt, ob_stats* st);
+double oracle_exchange_series(const ob_rad* p, double dt, int64_t nsteps, double* gas /*5*/, double* rad /*4*/,
+                              double* T4_out, int64_t every);
+void   oracle_rhd_step(const ob_box* b, double* Ug, double* Ur, const ob_rad* p, double dt_in, ob_stats* st);
+void   oracle_batch_step(int32_t nbox, const ob_box* boxes, double* const* Ug, double* const* Ur,
+                         double gamma_h, double cfl, const ob_rad* p, ob_stats* st);
+double oracle_closure_chi(double fhat, int closure);
+void   oracle_closure_pressure(double E, const double F[3], double c, int closure, double P[9]);
+void   oracle_ppm_cell(const double q[5], double out_aL_aR[2]);
+void   oracle_hllc(const double WL[5], const double WR[5], double gamma, double flux[5]);
+void   oracle_hll_rad(double EL, const double FL[3], double ER, const double FR[3], int dir,
+                      const ob_rad* p, double eps, double flux[4]);
+int    oracle_set_threads(int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,236 @@
+"""Seeded synthetic inputs for the per-cell update (shared by the GPU path's
+tests and benchmark and by the oracle's tests).
+
+This module holds workload recipes only: grid geometry, seeded random fields
+and the initial-condition definitions (ideal-gas energy E = P/(gamma-1) +
+rho v^2/2, E_r = a_r T_r^4).  It contains none of the update's arithmetic and
+imports neither the GPU binding nor the oracle.
+
+Every array is float64, C-contiguous, shape (nvar, nz+2ng, ny+2ng, nx+2ng),
+x fastest.  Ghost cells are left at zero unless a recipe defines them (the
+batched level, whose ghosts are fixed data); the path under test fills them.
+
+Draw order is fixed per recipe and documented in each function, so a seed
+fixes the input exactly.
+"""
+from __future__ import annotations
+
+from typing import NamedTuple, Optional, Sequence, Tuple
+
+import numpy as np
+
+PERIODIC, OUTFLOW, FIXED = 0, 1, 2
+
+
+class Box(NamedTuple):
+    n: Tuple[int, int, int]
+    ng: int
+    dx: Tuple[float, float, float]
+    bc: Tuple[Tuple[int, int], Tuple[int, int], Tuple[int, int]]
+    origin: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+
+    @property
+    def shape(self):
+        return (self.n[2] + 2 * self.ng, self.n[1] + 2 * self.ng, self.n[0] + 2 * self.ng)
+
+    def interior(self):
+        g = self.ng
+        return (slice(None), slice(g, g + self.n[2]), slice(g, g + self.n[1]), slice(g, g + self.n[0]))
+
+    @property
+    def ncells(self):
+        return int(self.n[0]) * int(self.n[1]) * int(self.n[2])
+
+
+def make_box(n, ng=4, L=1.0, bc=PERIODIC, origin=(0.0, 0.0, 0.0)) -> Box:
+    if isinstance(n, int):
+        n = (n, n, n)
+    if isinstance(L, (int, float)):
+        L = (float(L),) * 3
+    if isinstance(bc, int):
+        bc = ((bc, bc),) * 3
+    dx = tuple(float(L[d]) / n[d] for d in range(3))
+    return Box(tuple(int(v) for v in n), int(ng), dx, tuple(tuple(int(v) for v in p) for p in bc),
+               tuple(float(o) for o in origin))
+
+
+def cell_centres(b: Box, with_ghosts: bool = False):
+    """Cell-centre coordinates (z, y, x broadcastable), x_i = origin + (i + 1/2) dx."""
+    out = []
+    for d in (2, 1, 0):
+        if with_ghosts:
+            idx = np.arange(-b.ng, b.n[d] + b.ng, dtype=np.float64)
+        else:
+            idx = np.arange(b.n[d], dtype=np.float64)
+        out.append(b.origin[d] + (idx + 0.5) * b.dx[d])
+    z, y, x = out
+    return z[:, None, None], y[None, :, None], x[None, None, :]
+
+
+def _conserved(rho, vx, vy, vz, P, gamma):
+    E = P / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy + vz * vz)
+    return np.stack([rho, rho * vx, rho * vy, rho * vz, E])
+
+
+def _modes(rng, nmodes=4):
+    """Wave vectors drawn uniformly from {-2..2}^3 without 0, then phases in [0, 2 pi)."""
+    ks = []
+    while len(ks) < nmodes:
+        k = rng.integers(-2, 3, size=3)
+        if np.any(k != 0):
+            ks.append(k)
+    phis = rng.uniform(0.0, 2.0 * np.pi, size=nmodes)
+    return np.array(ks, dtype=np.float64), phis
+
+
+def _mode_sum(ks, phis, z, y, x):
+    s = 0.0
+    for k, ph in zip(ks, phis):
+        s = s + np.sin(2.0 * np.pi * (k[0] * x + k[1] * y + k[2] * z) + ph)
+    return s
+
+
+def _alloc(b: Box, nvar: int):
+    return np.zeros((nvar,) + b.shape, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Plain hydro, 32^3 periodic, gamma 5/3 (smooth density, random velocities).
+# Draws: 4 wave vectors + 4 phases, then vx, vy, vz per cell U[-0.1, 0.1].
+# ---------------------------------------------------------------------------
+def hydro_smooth(n=32, seed=1, gamma=5.0 / 3.0, ng=4):
+    b = make_box(n, ng=ng, bc=PERIODIC)
+    rng = np.random.default_rng(seed)
+    ks, phis = _modes(rng)
+    z, y, x = cell_centres(b)
+    rho = 1.0 + 0.1 * _mode_sum(ks, phis, z, y, x) * np.ones((b.n[2], b.n[1], b.n[0]))
+    v = rng.uniform(-0.1, 0.1, size=(3, b.n[2], b.n[1], b.n[0]))
+    P = np.ones_like(rho)
+    U = _alloc(b, 5)
+    U[b.interior()] = _conserved(rho, v[0], v[1], v[2], P, gamma)
+    return b, U, {"gamma": gamma, "cfl": 0.3}
+
+
+# ---------------------------------------------------------------------------
+# Plain hydro, one box n^3 (256 by default) with outflow boundaries, gamma 1.4:
+# planar discontinuity of seeded orientation through the centre
+# (rho 1 / 0.125, P 1 / 0.1, v = 0), density times (1 + 0.01 xi), xi U[-1,1].
+# Draws: normal = 3 standard normals (normalised), then xi per cell.
+# ---------------------------------------------------------------------------
+def hydro_shock(n=256, seed=2, gamma=1.4, ng=4):
+    b = make_box(n, ng=ng, bc=OUTFLOW)
+    rng = np.random.default_rng(seed)
+    nh = rng.normal(size=3)
+    nh = nh / np.sqrt(np.sum(nh * nh))
+    xi = rng.uniform(-1.0, 1.0, size=(b.n[2], b.n[1], b.n[0]))
+    z, y, x = cell_centres(b)
+    s = nh[0] * (x - 0.5) + nh[1] * (y - 0.5) + nh[2] * (z - 0.5)
+    left = s < 0.0
+    rho = np.where(left, 1.0, 0.125) * (1.0 + 0.01 * xi)
+    P = np.where(left, 1.0, 0.1) * np.ones_like(rho)
+    zero = np.zeros_like(rho)
+    U = _alloc(b, 5)
+    U[b.interior()] = _conserved(rho, zero, zero, zero, P, gamma)
+    return b, U, {"gamma": gamma, "cfl": 0.3, "normal": nh}
+
+
+# ---------------------------------------------------------------------------
+# Sedov-Taylor blast in [-1, 1]^3, periodic, rho 1, P 10 inside r < 0.1 else
+# 0.1, v = 0, gamma 5/3, CFL 0.25 (the paper's hydro performance workload).
+# No random draws.
+# ---------------------------------------------------------------------------
+def sedov(n=256, gamma=5.0 / 3.0, ng=4):
+    b = make_box(n, ng=ng, L=2.0, bc=PERIODIC, origin=(-1.0, -1.0, -1.0))
+    z, y, x = cell_centres(b)
+    r2 = x * x + y * y + z * z
+    P = np.where(r2 < 0.01, 10.0, 0.1) * np.ones((b.n[2], b.n[1], b.n[0]))
+    rho = np.ones_like(P)
+    zero = np.zeros_like(P)
+    U = _alloc(b, 5)
+    U[b.interior()] = _conserved(rho, zero, zero, zero, P, gamma)
+    return b, U, {"gamma": gamma, "cfl": 0.25}
+
+
+# ---------------------------------------------------------------------------
+# Radiation hydrodynamics, n^3 periodic, dimensionless units (P = rho T,
+# a_r = 1, c = 1000, gamma 5/3), constant grey opacity 1.
+# rho = exp(0.5 xi - 0.125), xi ~ N(0,1); T_gas, T_rad ~ U[0.5, 2] independent;
+# v = 0; E = rho T/(gamma-1); E_r = a_r T_rad^4; F = 0;
+# chat = 10 x max over cells of sqrt(gamma T).
+# Draws: xi per cell, then T_gas per cell, then T_rad per cell.
+# ---------------------------------------------------------------------------
+def rad_params(chat, gamma=5.0 / 3.0, **kw):
+    p = {"c": 1000.0, "chat": float(chat), "a_r": 1.0, "kappa_P": 1.0, "kappa_R": 1.0, "gamma": gamma,
+         "alpha_cv": 4.0, "cfl": 0.3, "newton_tol": 1e-12, "newton_max_iter": 400, "nsub_max": 10,
+         "closure": 0, "tau_correction": 1, "eos": 0}
+    p.update(kw)
+    return p
+
+
+def rhd_lognormal(n=128, seed=3, gamma=5.0 / 3.0, ng=4):
+    b = make_box(n, ng=ng, bc=PERIODIC)
+    rng = np.random.default_rng(seed)
+    shape = (b.n[2], b.n[1], b.n[0])
+    xi = rng.normal(size=shape)
+    rho = np.exp(0.5 * xi - 0.125)
+    Tg = rng.uniform(0.5, 2.0, size=shape)
+    Tr = rng.uniform(0.5, 2.0, size=shape)
+    a_r = 1.0
+    zero = np.zeros(shape)
+    Ug = _alloc(b, 5)
+    Ug[b.interior()] = _conserved(rho, zero, zero, zero, rho * Tg, gamma)
+    Ur = _alloc(b, 4)
+    Ur[(0,) + b.interior()[1:]] = a_r * Tr ** 4
+    chat = 10.0 * float(np.sqrt(gamma * Tg.max()))
+    return b, Ug, Ur, rad_params(chat, gamma)
+
+
+# ---------------------------------------------------------------------------
+# Batched AMR-like level: nbox boxes, each axis edge i.i.d. from
+# {8,16,24,32,48,64}, dx = 1/256, origin U[0,1)^3, RHD with probability 1/2.
+# Interior and the 4 ghost layers are filled from smooth seeded fields:
+# rho = 1 + 0.1 s1, P = 1 + 0.05 s2, v_d = 0.05 s_{3+d}; RHD boxes also get
+# T_r = (P/rho)(1 + 0.05 s6), E_r = a_r T_r^4, F = 0 (s_i = sum of 4 modes).
+# Ghosts are fixed data (the boundary kind of every face is FIXED).
+# Draws: 6 mode sets, then per box: 3 edges, 3 origin coordinates, 1 type draw.
+# ---------------------------------------------------------------------------
+EDGES = (8, 16, 24, 32, 48, 64)
+
+
+def batch_level(nbox=600, seed=5, gamma=5.0 / 3.0, ng=4, edges: Optional[Sequence[int]] = None,
+                rad_fraction=0.5):
+    rng = np.random.default_rng(seed)
+    modes = [_modes(rng) for _ in range(6)]
+    edges = EDGES if edges is None else tuple(edges)
+    boxes, Ugs, Urs = [], [], []
+    dx = 1.0 / 256.0
+    cmax = 0.0
+    for _ in range(nbox):
+        n = tuple(int(edges[i]) for i in rng.integers(0, len(edges), size=3))
+        origin = tuple(float(o) for o in rng.uniform(0.0, 1.0, size=3))
+        is_rad = bool(rng.uniform() < rad_fraction)
+        b = Box(n, ng, (dx, dx, dx), ((FIXED, FIXED),) * 3, origin)
+        z, y, x = cell_centres(b, with_ghosts=True)
+        full = np.ones(b.shape)
+        s = [_mode_sum(k, p, z, y, x) * full for (k, p) in modes]
+        rho = 1.0 + 0.1 * s[0]
+        P = 1.0 + 0.05 * s[1]
+        vx, vy, vz = 0.05 * s[2], 0.05 * s[3], 0.05 * s[4]
+        Ug = np.ascontiguousarray(_conserved(rho, vx, vy, vz, P, gamma))
+        Ur = None
+        if is_rad:
+            T = P / rho
+            Tr = T * (1.0 + 0.05 * s[5])
+            Ur = np.zeros((4,) + b.shape)
+            Ur[0] = Tr ** 4
+            cmax = max(cmax, float(np.sqrt(gamma * T.max())))
+        boxes.append(b)
+        Ugs.append(Ug)
+        Urs.append(Ur)
+    chat = 10.0 * cmax if cmax > 0 else 10.0
+    return boxes, Ugs, Urs, rad_params(chat, gamma), {"gamma": gamma, "cfl": 0.3}
+
+
+def to_f32_and_back(U):
+    """FP32-rounded copy promoted exactly back to float64 (mixed-precision reference start)."""
+    return U.astype(np.float32).astype(np.float64)
