@@ -1,0 +1,180 @@
+/*
+ * quokka.h -- C ABI of the MI355X (gfx950) library for the explicit per-cell
+ * radiation-hydrodynamics update of Wibking & Krumholz (2021), "QUOKKA: a code
+ * for two-moment AMR radiation hydrodynamics on GPUs" (arXiv:2110.01792).
+ *
+ * Library: libquokka_mi355x.so (HIP).  Every state pointer is a DEVICE pointer
+ * owned by the caller; the library never frees caller memory.  Calls are
+ * asynchronous on the given HIP stream (NULL = default stream) unless stated.
+ *
+ * State layout (every entry point): structure of arrays, variable-major, x
+ * fastest, ghost cells included:
+ *     U[v * var_stride + (k + ng) * pitch_z + (j + ng) * pitch_y + (i + ng)]
+ * for interior cells 0 <= i < n[0], 0 <= j < n[1], 0 <= k < n[2].
+ * Gas state: 5 variables (rho, rho vx, rho vy, rho vz, E)       (Section 3.1.1)
+ * Radiation:  4 variables (E_r, F_x, F_y, F_z)                    (Section 2.1)
+ * Element type: double for QK_F64, float for QK_MIXED.
+ *
+ * Errors: argument errors are detected on the host and returned at once with
+ * no work queued (QK_EINVAL).  Conditions found on the device (non-positive
+ * density, pressure or radiation energy; an exchange solve that reaches its
+ * iteration cap) set sticky bits in the context's device error word; they are
+ * reported by the next call that synchronises (quokka_sync_status, or any call
+ * given a non-NULL dt_host).  The library never exits or aborts.
+ *
+ * Threading: a context serves one stream at a time; calls on one context that
+ * overlap in time race on its scratch memory.
+ */
+#ifndef QUOKKA_H
+#define QUOKKA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qk_ctx qk_ctx;
+
+typedef enum {
+  QK_OK = 0,
+  QK_EINVAL = 1,     /* bad argument (detected on the host, nothing queued) */
+  QK_ENOMEM = 2,     /* device allocation failed */
+  QK_EHIP = 3,       /* a HIP runtime call failed */
+  QK_ENEGATIVE = 4,  /* rho <= 0, P <= 0 or E_r <= 0 met on the device */
+  QK_ENEWTON = 5     /* an exchange solve hit newton_max_iter (Section 2.2.3) */
+} qk_status;
+
+/* QK_MIXED: float state arrays, float reconstruction and flux arithmetic;
+ * double for E - rho v^2/2, the exchange solve and the stage accumulation. */
+typedef enum { QK_F64 = 0, QK_MIXED = 1 } qk_precision;
+
+/* Boundary kind per box face.  PERIODIC must pair (lo and hi of one axis).
+ * FIXED: the ghost cells are caller data and are never written. */
+typedef enum { QK_BC_PERIODIC = 0, QK_BC_OUTFLOW = 1, QK_BC_FIXED = 2 } qk_bc;
+
+typedef struct {
+  int32_t n[3];        /* interior cells per axis, each >= 1                    */
+  int32_t ng;          /* ghost layers, >= 4 (PPM needs +-2, flattening +-3, and
+                          the face next to the boundary the flattening of the
+                          first ghost cell)                                       */
+  int64_t pitch_y;     /* element stride between rows;   0 = n[0] + 2 ng          */
+  int64_t pitch_z;     /* element stride between planes; 0 = pitch_y (n[1]+2ng) */
+  int64_t var_stride;  /* element stride between variables; 0 = pitch_z (n[2]+2ng) */
+  double dx[3];        /* cell widths                                           */
+  int32_t bc[3][2];    /* qk_bc per axis, lo then hi                            */
+} qk_box;
+
+/* Hydrodynamics (Section 2.2.1): PPM in primitive variables with
+ * multidimensional shock flattening, HLLC with PVRS wave speeds, SSP-RK2. */
+typedef struct {
+  double gamma;  /* ideal-gas adiabatic index */
+  double cfl;    /* CFL number C0/D: dt = cfl * min(dx) / max(|v| + c_s) */
+} qk_hydro_params;
+
+/* Radiation (Sections 2.1, 2.2.2, 2.2.3) under the reduced speed of light. */
+typedef struct {
+  double c, chat;         /* speed of light and its reduced value              */
+  double a_r;             /* radiation constant                                */
+  double kappa_P, kappa_R;/* Planck and Rosseland mean opacities (constant)     */
+  double gamma;           /* gas adiabatic index                               */
+  double alpha_cv;        /* eos 1: E_g = alpha_cv T^4 / 4 (C_v = alpha T^3)   */
+  double cfl;             /* radiation substep dt_r = cfl * min(dx) / chat     */
+  double newton_tol;      /* relative tolerance of the exchange solve          */
+  int32_t newton_max_iter;/* iteration cap (400 in the paper)                  */
+  int32_t nsub_max;       /* substep cap per hydro step (10 in the paper)      */
+  int32_t closure;        /* 0 Levermore (M1), 1 Eddington (P = E/3 I)         */
+  int32_t tau_correction; /* 1: scale HLL dissipation by min(1, 1/tau_face)    */
+  int32_t eos;            /* 0: P = rho T, E_g = rho T/(gamma-1); 1: alpha T^4 */
+} qk_rad_params;
+
+/* Create a context on HIP device `device` (its scratch, device error word and
+ * batch-graph cache).  Returns QK_EINVAL for a bad device index. */
+qk_status quokka_ctx_create(int device, qk_ctx** out);
+void quokka_ctx_destroy(qk_ctx* ctx);
+/* Text of the last error on this context (static storage of the context). */
+const char* quokka_last_error(const qk_ctx* ctx);
+
+/* Fill the ghost cells of `nvar` variables: periodic wrap, zero-gradient
+ * outflow (copy of the nearest interior cell), fixed left untouched; edges
+ * and corners as by an x, then y, then z sequential fill. */
+qk_status quokka_fill_ghosts(qk_ctx* ctx, const qk_box* box, void* U, int32_t nvar, qk_precision prec,
+                             void* stream);
+
+/* Time step of one (R)HD step from the gas state (Section 2.2.1 eq. signal and
+ * the dt that follows): dt = cfl * min(dx) / max over interior (|v| + c_s).
+ * With rp != NULL also the radiation substep count (Section 2.2.4):
+ * N = ceil(dt / dt_r), dt_r = rp->cfl * min(dx) / chat; if N > nsub_max then
+ * N = nsub_max and dt = N dt_r.  Results go to dt_dev / nsub_dev (device,
+ * either may be NULL) and, if dt_host != NULL, to the host (synchronises and
+ * reports sticky device errors). */
+qk_status quokka_compute_dt(qk_ctx* ctx, const qk_box* box, const void* U_gas, qk_precision prec,
+                            const qk_hydro_params* hp, const qk_rad_params* rp, double* dt_dev,
+                            int32_t* nsub_dev, double* dt_host, void* stream);
+
+/* One SSP-RK2 hydro step in place (Section 2.2.1).  The input ghosts must be
+ * valid (quokka_fill_ghosts); the output ghosts are refilled.  dt: read from
+ * dt_dev if non-NULL, else dt_in if > 0, else computed from U as in
+ * quokka_compute_dt.  If dt_next_dev != NULL the CFL dt of the new state is
+ * written there (fused into the second stage; no extra pass). */
+qk_status quokka_hydro_step(qk_ctx* ctx, const qk_box* box, void* U_gas, qk_precision prec,
+                            const qk_hydro_params* hp, const double* dt_dev, double dt_in, double* dt_next_dev,
+                            void* stream);
+
+/* Radiation subsystem over one hydro step (Sections 2.2.2, 2.2.3): N times
+ * { RK2 transport of (E_r, F) with dt/N; per-cell implicit exchange, flux
+ * source, momentum and work terms }, updating U_rad and (momentum, energy of)
+ * U_gas.  dt and N are read from dt_dev / nsub_dev (as written by
+ * quokka_compute_dt) if non-NULL, else N = ceil(dt_in / dt_r), which must not
+ * exceed nsub_max (QK_EINVAL otherwise).  Gas ghosts must be valid (density is
+ * read at faces); all ghosts are refilled at the end. */
+qk_status quokka_rad_step(qk_ctx* ctx, const qk_box* box, void* U_gas, void* U_rad, qk_precision prec,
+                          const qk_rad_params* rp, const double* dt_dev, const int32_t* nsub_dev, double dt_in,
+                          void* stream);
+
+/* One radiation-hydrodynamics step (Section 2.2 operator split): compute_dt
+ * with the substep cap, hydro step, radiation step.  dt_host as in
+ * quokka_compute_dt (receives the hydro dt taken). */
+qk_status quokka_rhd_step(qk_ctx* ctx, const qk_box* box, void* U_gas, void* U_rad, qk_precision prec,
+                          const qk_rad_params* rp, double* dt_host, void* stream);
+
+/* One level step over nbox independent boxes whose ghosts are FIXED data
+ * (every bc entry must be QK_BC_FIXED): one level-wide hydro dt (minimum CFL
+ * step over boxes; hydro-only boxes use hp->gamma, radiation boxes rp->gamma),
+ * shrunk as in quokka_compute_dt when any box carries radiation; every box
+ * advanced with it; U_rad[i] == NULL marks a hydro-only box.  Each RK stage of
+ * every box runs in one persistent launch over a (box, tile) work list; the
+ * whole step is captured once per box list into a HIP graph and replayed.
+ * boxes, U_gas and U_rad are host arrays of length nbox. */
+qk_status quokka_batch_step(qk_ctx* ctx, const qk_box* boxes, int32_t nbox, void* const* U_gas,
+                            void* const* U_rad, qk_precision prec, const qk_hydro_params* hp,
+                            const qk_rad_params* rp, double* dt_host, void* stream);
+
+/* Wait for the stream, then return and clear the first sticky device error
+ * (QK_ENEGATIVE, QK_ENEWTON) or QK_OK. */
+qk_status quokka_sync_status(qk_ctx* ctx, void* stream);
+
+/* Number of exchange-solve iterations of the slowest cell since the last call
+ * (synchronises; resets the counter). */
+int32_t quokka_newton_iter_max(qk_ctx* ctx, void* stream);
+
+/* Measurement: while enabled, every launch of a kernel class is bracketed by
+ * HIP events recorded on the stream it is launched on.  quokka_kernel_time
+ * synchronises and returns the summed event time (ms) and launch count of a
+ * class since timing was (re)enabled. */
+typedef enum {
+  QK_K_HYDRO_STAGE = 0, /* fused hydro RK stage (both stages) */
+  QK_K_FLATTEN = 1,     /* shock-flattening pass              */
+  QK_K_RAD_STAGE = 2,   /* radiation RK stage 1               */
+  QK_K_RAD_COUPLE = 3,  /* radiation RK stage 2 + coupling    */
+  QK_K_GHOST = 4,       /* ghost fill                         */
+  QK_K_BATCH = 5,       /* persistent batched stage kernels   */
+  QK_K_NCLASS = 6
+} qk_kernel_class;
+qk_status quokka_timing(qk_ctx* ctx, int32_t enable);
+qk_status quokka_kernel_time(qk_ctx* ctx, int32_t kclass, double* ms_total, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,230 @@
+"""ctypes binding of libquokka_mi355x.so (C ABI in include/quokka.h).
+
+Argument marshalling only: every step of the update runs in the HIP library.
+State arguments are torch tensors on a ROCm device (float64 for F64, float32
+for MIXED), shape (nvar, nz+2ng, ny+2ng, nx+2ng), contiguous; PyTorch supplies
+device memory and streams, nothing else.  If the library is missing this
+module raises; there is no fallback.
+"""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libquokka_mi355x.so")
+
+QK_OK, QK_EINVAL, QK_ENOMEM, QK_EHIP, QK_ENEGATIVE, QK_ENEWTON = range(6)
+F64, MIXED = 0, 1
+STATUS_NAMES = {0: "QK_OK", 1: "QK_EINVAL", 2: "QK_ENOMEM", 3: "QK_EHIP", 4: "QK_ENEGATIVE", 5: "QK_ENEWTON"}
+
+EXPORTED = ("quokka_ctx_create", "quokka_ctx_destroy", "quokka_last_error", "quokka_fill_ghosts",
+            "quokka_compute_dt", "quokka_hydro_step", "quokka_rad_step", "quokka_rhd_step", "quokka_batch_step",
+            "quokka_sync_status", "quokka_newton_iter_max", "quokka_timing", "quokka_kernel_time")
+K_HYDRO_STAGE, K_FLATTEN, K_RAD_STAGE, K_RAD_COUPLE, K_GHOST, K_BATCH = range(6)
+
+
+class QkBox(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("ng", ctypes.c_int32), ("pitch_y", ctypes.c_int64),
+                ("pitch_z", ctypes.c_int64), ("var_stride", ctypes.c_int64), ("dx", ctypes.c_double * 3),
+                ("bc", (ctypes.c_int32 * 2) * 3)]
+
+
+class QkHydroParams(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double)]
+
+
+class QkRadParams(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_double), ("chat", ctypes.c_double), ("a_r", ctypes.c_double),
+                ("kappa_P", ctypes.c_double), ("kappa_R", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("alpha_cv", ctypes.c_double), ("cfl", ctypes.c_double), ("newton_tol", ctypes.c_double),
+                ("newton_max_iter", ctypes.c_int32), ("nsub_max", ctypes.c_int32), ("closure", ctypes.c_int32),
+                ("tau_correction", ctypes.c_int32), ("eos", ctypes.c_int32)]
+
+
+class QuokkaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2110_01792_amd/build.py "
+                           "(or __graft_entry__.build()); there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, V, I32, D = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    sigs = {
+        "quokka_ctx_create": (ctypes.c_int, [ctypes.c_int, P(V)]),
+        "quokka_ctx_destroy": (None, [V]),
+        "quokka_last_error": (ctypes.c_char_p, [V]),
+        "quokka_fill_ghosts": (ctypes.c_int, [V, P(QkBox), V, I32, ctypes.c_int, V]),
+        "quokka_compute_dt": (ctypes.c_int, [V, P(QkBox), V, ctypes.c_int, P(QkHydroParams), P(QkRadParams), V, V,
+                                             P(D), V]),
+        "quokka_hydro_step": (ctypes.c_int, [V, P(QkBox), V, ctypes.c_int, P(QkHydroParams), V, D, V, V]),
+        "quokka_rad_step": (ctypes.c_int, [V, P(QkBox), V, V, ctypes.c_int, P(QkRadParams), V, V, D, V]),
+        "quokka_rhd_step": (ctypes.c_int, [V, P(QkBox), V, V, ctypes.c_int, P(QkRadParams), P(D), V]),
+        "quokka_batch_step": (ctypes.c_int, [V, P(QkBox), I32, P(V), P(V), ctypes.c_int, P(QkHydroParams),
+                                             P(QkRadParams), P(D), V]),
+        "quokka_sync_status": (ctypes.c_int, [V, V]),
+        "quokka_newton_iter_max": (I32, [V, V]),
+        "quokka_timing": (ctypes.c_int, [V, I32]),
+        "quokka_kernel_time": (ctypes.c_int, [V, I32, P(D), P(ctypes.c_int64)]),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def make_box(b):
+    """QkBox from any object with n, ng, dx, bc (contiguous layout)."""
+    q = QkBox()
+    for d in range(3):
+        q.n[d] = int(b.n[d])
+        q.dx[d] = float(b.dx[d])
+        q.bc[d][0] = int(b.bc[d][0])
+        q.bc[d][1] = int(b.bc[d][1])
+    q.ng = int(b.ng)
+    q.pitch_y = q.pitch_z = q.var_stride = 0
+    return q
+
+
+def hydro_params(gamma, cfl):
+    return QkHydroParams(float(gamma), float(cfl))
+
+
+def rad_params(p):
+    r = QkRadParams()
+    for k in ("c", "chat", "a_r", "kappa_P", "kappa_R", "gamma", "alpha_cv", "cfl", "newton_tol"):
+        setattr(r, k, float(p[k]))
+    for k in ("newton_max_iter", "nsub_max", "closure", "tau_correction", "eos"):
+        setattr(r, k, int(p[k]))
+    return r
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _prec_of(t):
+    import torch
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return MIXED
+    raise TypeError(f"state dtype {t.dtype} is neither float64 nor float32")
+
+
+def _check_state(t, b, nvar):
+    shape = (nvar, b.n[2] + 2 * b.ng, b.n[1] + 2 * b.ng, b.n[0] + 2 * b.ng)
+    if tuple(t.shape) != shape:
+        raise ValueError(f"state shape {tuple(t.shape)} != {shape}")
+    if not t.is_contiguous() or t.device.type != "cuda":
+        raise ValueError("state must be a contiguous device tensor")
+
+
+class Context:
+    """One library context on one device."""
+
+    def __init__(self, device=0):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        st = self.lib.quokka_ctx_create(int(device), ctypes.byref(h))
+        if st != QK_OK:
+            raise QuokkaError(st, f"cannot create a context on device {device}")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.quokka_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ok(self, st):
+        if st != QK_OK:
+            raise QuokkaError(st, self.lib.quokka_last_error(self.h).decode())
+
+    def fill_ghosts(self, b, U, stream=None):
+        _check_state(U, b, U.shape[0])
+        self._ok(self.lib.quokka_fill_ghosts(self.h, ctypes.byref(make_box(b)), _ptr(U), int(U.shape[0]),
+                                             _prec_of(U), _stream(stream)))
+
+    def compute_dt(self, b, Ug, hp=None, rp=None, dt_dev=None, nsub_dev=None, host=True, stream=None):
+        _check_state(Ug, b, 5)
+        out = ctypes.c_double(0.0)
+        self._ok(self.lib.quokka_compute_dt(self.h, ctypes.byref(make_box(b)), _ptr(Ug), _prec_of(Ug),
+                                            ctypes.byref(hp) if hp is not None else None,
+                                            ctypes.byref(rp) if rp is not None else None, _ptr(dt_dev),
+                                            _ptr(nsub_dev), ctypes.byref(out) if host else None, _stream(stream)))
+        return out.value if host else None
+
+    def hydro_step(self, b, Ug, hp, dt_dev=None, dt=0.0, dt_next_dev=None, stream=None):
+        _check_state(Ug, b, 5)
+        self._ok(self.lib.quokka_hydro_step(self.h, ctypes.byref(make_box(b)), _ptr(Ug), _prec_of(Ug),
+                                            ctypes.byref(hp), _ptr(dt_dev), float(dt), _ptr(dt_next_dev),
+                                            _stream(stream)))
+
+    def rad_step(self, b, Ug, Ur, rp, dt_dev=None, nsub_dev=None, dt=0.0, stream=None):
+        _check_state(Ug, b, 5)
+        _check_state(Ur, b, 4)
+        self._ok(self.lib.quokka_rad_step(self.h, ctypes.byref(make_box(b)), _ptr(Ug), _ptr(Ur), _prec_of(Ug),
+                                          ctypes.byref(rp), _ptr(dt_dev), _ptr(nsub_dev), float(dt),
+                                          _stream(stream)))
+
+    def rhd_step(self, b, Ug, Ur, rp, host_dt=False, stream=None):
+        _check_state(Ug, b, 5)
+        _check_state(Ur, b, 4)
+        out = ctypes.c_double(0.0)
+        self._ok(self.lib.quokka_rhd_step(self.h, ctypes.byref(make_box(b)), _ptr(Ug), _ptr(Ur), _prec_of(Ug),
+                                          ctypes.byref(rp), ctypes.byref(out) if host_dt else None,
+                                          _stream(stream)))
+        return out.value if host_dt else None
+
+    def batch_step(self, boxes, Ugs, Urs, hp, rp, host_dt=True, stream=None):
+        n = len(boxes)
+        arr = (QkBox * n)(*[make_box(b) for b in boxes])
+        gp = (ctypes.c_void_p * n)(*[u.data_ptr() for u in Ugs])
+        rpp = (ctypes.c_void_p * n)(*[(u.data_ptr() if u is not None else None) for u in Urs])
+        out = ctypes.c_double(0.0)
+        self._ok(self.lib.quokka_batch_step(self.h, arr, n, gp, rpp, _prec_of(Ugs[0]), ctypes.byref(hp),
+                                            ctypes.byref(rp) if rp is not None else None,
+                                            ctypes.byref(out) if host_dt else None, _stream(stream)))
+        return out.value if host_dt else None
+
+    def sync_status(self, stream=None):
+        return self.lib.quokka_sync_status(self.h, _stream(stream))
+
+    def newton_iter_max(self, stream=None):
+        return self.lib.quokka_newton_iter_max(self.h, _stream(stream))
+
+    def timing(self, enable):
+        self._ok(self.lib.quokka_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self, kclass):
+        """(total ms, launches) of a kernel class since timing was enabled."""
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int64(0)
+        self._ok(self.lib.quokka_kernel_time(self.h, int(kclass), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

@@ -1,0 +1,484 @@
+// C ABI of the MI355X per-cell update library (declarations and contracts in
+// include/quokka.h).  Host-side validation, scratch management and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "quokka.h"
+#include "hydro_kernels.hpp"
+#include "rad_kernels.hpp"
+#include "batch.hpp"
+
+using namespace qk;
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+namespace {
+// Device scalar block (one allocation): accumulators and step scalars.
+struct Scalars {
+  unsigned long long smax_a;  // CFL accumulator for compute_dt
+  unsigned long long smax_b;  // CFL accumulator for dt_next of a hydro step
+  double dt;                  // step dt written by compute_dt
+  double dt_aux;
+  int32_t nsub;
+  uint32_t err;               // sticky ERR_* bits
+  uint32_t newton_iter_max;
+  uint32_t pad[9];
+};
+
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+}  // namespace
+
+// Event pairs around kernel launches of one class (measurement only).
+struct KernelTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void begin(int cls, hipStream_t s) {
+    if (!on) return;
+    Rec r{cls, get(), get()};
+    if (!r.a || !r.b) return;
+    (void)hipEventRecord(r.a, s);
+    recs.push_back(r);
+  }
+  void end(int cls, hipStream_t s) {
+    if (!on || recs.empty() || recs.back().cls != cls) return;
+    (void)hipEventRecord(recs.back().b, s);
+  }
+  void reset() {
+    recs.clear();
+    used = 0;
+  }
+  ~KernelTimer() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+struct qk_ctx {
+  int device = 0;
+  std::string last_error;
+  Scalars* sc = nullptr;
+  Buf stage_g, stage_r, chi;
+  BatchCache batch;
+  KernelTimer timer;
+};
+
+namespace {
+
+qk_status fail(qk_ctx* ctx, qk_status st, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return st;
+}
+
+qk_status hip_check(qk_ctx* ctx, hipError_t e, const char* what) {
+  if (e == hipSuccess) return QK_OK;
+  return fail(ctx, QK_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+qk_status ensure(qk_ctx* ctx, Buf& b, size_t bytes) {
+  if (b.bytes >= bytes) return QK_OK;
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+  if (hipMalloc(&b.p, bytes) != hipSuccess) return fail(ctx, QK_ENOMEM, "scratch allocation failed");
+  b.bytes = bytes;
+  return QK_OK;
+}
+
+// Full geometry of a validated box.
+struct HostBox {
+  DevBox d;
+  int64_t elems;  // var_stride
+  int bc[3][2];
+  bool any_fixed;
+};
+
+qk_status check_box(qk_ctx* ctx, const qk_box* b, HostBox& hb) {
+  if (!b) return fail(ctx, QK_EINVAL, "box is NULL");
+  for (int d = 0; d < 3; ++d) {
+    if (b->n[d] < 1) return fail(ctx, QK_EINVAL, "box extent < 1");
+    if (!(b->dx[d] > 0.0) || !std::isfinite(b->dx[d])) return fail(ctx, QK_EINVAL, "cell width must be > 0");
+    for (int s = 0; s < 2; ++s)
+      if (b->bc[d][s] < 0 || b->bc[d][s] > 2) return fail(ctx, QK_EINVAL, "unknown boundary kind");
+    if ((b->bc[d][0] == QK_BC_PERIODIC) != (b->bc[d][1] == QK_BC_PERIODIC))
+      return fail(ctx, QK_EINVAL, "periodic boundaries must pair");
+  }
+  if (b->ng < 4) return fail(ctx, QK_EINVAL, "ng must be >= 4");
+  const int64_t NX = b->n[0] + 2 * (int64_t)b->ng, NY = b->n[1] + 2 * (int64_t)b->ng,
+                NZ = b->n[2] + 2 * (int64_t)b->ng;
+  const int64_t py = b->pitch_y ? b->pitch_y : NX;
+  const int64_t pz = b->pitch_z ? b->pitch_z : py * NY;
+  const int64_t vs = b->var_stride ? b->var_stride : pz * NZ;
+  if (py < NX || pz < py * NY || vs < pz * NZ) return fail(ctx, QK_EINVAL, "pitches too small for the extents");
+  if (vs * 5 > ((int64_t)1 << 40)) return fail(ctx, QK_EINVAL, "box too large");
+  DevBox& d = hb.d;
+  d.n0 = b->n[0];
+  d.n1 = b->n[1];
+  d.n2 = b->n[2];
+  d.ng = b->ng;
+  d.py = py;
+  d.pz = pz;
+  d.vs = vs;
+  d.dx0 = b->dx[0];
+  d.dx1 = b->dx[1];
+  d.dx2 = b->dx[2];
+  d.inv_dx0 = 1.0 / b->dx[0];
+  d.inv_dx1 = 1.0 / b->dx[1];
+  d.inv_dx2 = 1.0 / b->dx[2];
+  d.dxmin = std::min(b->dx[0], std::min(b->dx[1], b->dx[2]));
+  hb.elems = vs;
+  hb.any_fixed = false;
+  for (int a = 0; a < 3; ++a)
+    for (int s = 0; s < 2; ++s) {
+      hb.bc[a][s] = b->bc[a][s];
+      if (b->bc[a][s] == QK_BC_FIXED) hb.any_fixed = true;
+    }
+  return QK_OK;
+}
+
+qk_status check_prec(qk_ctx* ctx, qk_precision p) {
+  if (p != QK_F64 && p != QK_MIXED) return fail(ctx, QK_EINVAL, "unknown precision");
+  return QK_OK;
+}
+
+qk_status check_hydro(qk_ctx* ctx, const qk_hydro_params* hp) {
+  if (!hp) return fail(ctx, QK_EINVAL, "hydro params NULL");
+  if (!(hp->gamma > 1.0) || !(hp->cfl > 0.0)) return fail(ctx, QK_EINVAL, "need gamma > 1 and cfl > 0");
+  return QK_OK;
+}
+
+qk_status check_rad(qk_ctx* ctx, const qk_rad_params* rp) {
+  if (!rp) return fail(ctx, QK_EINVAL, "rad params NULL");
+  if (!(rp->c > 0) || !(rp->chat > 0) || !(rp->a_r > 0) || !(rp->gamma > 1.0) || !(rp->cfl > 0) ||
+      !(rp->newton_tol > 0) || rp->newton_max_iter < 1 || rp->nsub_max < 1 || rp->closure < 0 ||
+      rp->closure > 1 || rp->eos < 0 || rp->eos > 1 || !(rp->kappa_P >= 0) || !(rp->kappa_R >= 0) ||
+      (rp->eos == 1 && !(rp->alpha_cv > 0)))
+    return fail(ctx, QK_EINVAL, "invalid radiation parameters");
+  return QK_OK;
+}
+
+GhostBC ghost_bc(const HostBox& hb) {
+  GhostBC g;
+  for (int a = 0; a < 3; ++a) {
+    g.lo[a] = hb.bc[a][0];
+    g.hi[a] = hb.bc[a][1];
+  }
+  return g;
+}
+
+int grid_for(int64_t n, int per_block, int cap) {
+  int64_t g = (n + per_block - 1) / per_block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
+}
+
+template <class S>
+void launch_ghosts(const HostBox& hb, S* U, int nvar, hipStream_t s) {
+  const DevBox& d = hb.d;
+  const int64_t NX = d.n0 + 2 * d.ng, NY = d.n1 + 2 * d.ng;
+  const int64_t total = 2 * d.ng * NY * NX + 2 * d.ng * d.n2 * NX + 2 * d.ng * (int64_t)d.n2 * d.n1;
+  bool all_fixed = true;
+  for (int a = 0; a < 3; ++a)
+    for (int t = 0; t < 2; ++t) all_fixed = all_fixed && hb.bc[a][t] == QK_BC_FIXED;
+  if (all_fixed) return;
+  hipLaunchKernelGGL(ghost_kernel<S>, dim3(grid_for(total, 256, 4096)), dim3(256), 0, s, U, d, ghost_bc(hb), nvar);
+}
+
+template <class S>
+void launch_ghost_copy(const HostBox& hb, S* dst, const S* src, int nvar, hipStream_t s) {
+  const DevBox& d = hb.d;
+  const int64_t total = (int64_t)(d.n0 + 2 * d.ng) * (d.n1 + 2 * d.ng) * (d.n2 + 2 * d.ng);
+  hipLaunchKernelGGL(ghost_copy_kernel<S>, dim3(grid_for(total, 256, 8192)), dim3(256), 0, s, dst, src, d, nvar);
+}
+
+// Tile shape and z-chunk of the hydro stage for one box.
+constexpr int HTX = 16, HTY = 16;
+
+struct Launch {
+  int gx, gy, gz, zc;
+};
+
+Launch plan(int n0, int n1, int n2, int tx, int ty, int target_blocks) {
+  Launch L;
+  L.gx = (n0 + tx - 1) / tx;
+  L.gy = (n1 + ty - 1) / ty;
+  const int nxy = L.gx * L.gy;
+  int chunks = std::max(1, std::min(n2, (target_blocks + nxy - 1) / nxy));
+  // keep at least 8 planes per chunk so the z prologue stays a small fraction
+  chunks = std::max(1, std::min(chunks, std::max(1, n2 / 8)));
+  L.zc = (n2 + chunks - 1) / chunks;
+  L.gz = (n2 + L.zc - 1) / L.zc;
+  return L;
+}
+
+template <class S, class R>
+void launch_flatten(const HostBox& hb, const S* U, R* chi, double gamma, hipStream_t s) {
+  const DevBox& d = hb.d;
+  Launch L = plan(d.n0 + 2, d.n1 + 2, d.n2 + 2, HTX, HTY, 2048);
+  hipLaunchKernelGGL((flatten_kernel<S, R, HTX, HTY>), dim3(L.gx * L.gy * L.gz), dim3(HTX * HTY), 0, s, U, chi, d,
+                     gamma - 1.0, L.zc, L.gx, L.gy);
+}
+
+template <class S, class R, int STAGE>
+void launch_stage(const HostBox& hb, const S* Uin, const S* Un, S* Uout, const R* chi, double gamma,
+                  const double* dt_ptr, double dt_val, unsigned long long* smax, uint32_t* err, hipStream_t s) {
+  const DevBox& d = hb.d;
+  Launch L = plan(d.n0, d.n1, d.n2, HTX, HTY, 2048);
+  StageArgs<S, R> a;
+  a.Uin = Uin;
+  a.Un = Un;
+  a.Uout = Uout;
+  a.chi = chi;
+  a.b = d;
+  a.gamma = gamma;
+  a.dt_ptr = dt_ptr;
+  a.dt_val = dt_val;
+  a.zc = L.zc;
+  a.gx = L.gx;
+  a.gy = L.gy;
+  a.smax = smax;
+  a.err = err;
+  hipLaunchKernelGGL((stage_kernel<S, R, HTX, HTY, STAGE>), dim3(L.gx * L.gy * L.gz), dim3(HTX * HTY), 0, s, a);
+}
+
+template <class S>
+void launch_max_signal(const HostBox& hb, const S* U, double gamma, unsigned long long* acc, uint32_t* err,
+                       hipStream_t s) {
+  const int64_t n = (int64_t)hb.d.n0 * hb.d.n1 * hb.d.n2;
+  hipLaunchKernelGGL((max_signal_kernel<S, 256>), dim3(grid_for(n, 256 * 8, 2048)), dim3(256), 0, s, U, hb.d,
+                     gamma, acc, err);
+}
+
+// dt of the hydro step: device pointer to use (possibly computed here)
+template <class S>
+const double* resolve_dt(qk_ctx* ctx, const HostBox& hb, const S* U, double gamma, double cfl, const double* dt_dev,
+                         double dt_in, double* dt_val, hipStream_t s) {
+  *dt_val = dt_in;
+  if (dt_dev) return dt_dev;
+  if (dt_in > 0.0) return nullptr;
+  launch_max_signal<S>(hb, U, gamma, &ctx->sc->smax_a, &ctx->sc->err, s);
+  hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(64), 0, s, &ctx->sc->smax_a, cfl, hb.d.dxmin, 0.0, 0,
+                     &ctx->sc->dt, (int32_t*)nullptr);
+  return &ctx->sc->dt;
+}
+
+template <class S, class R>
+qk_status hydro_step_t(qk_ctx* ctx, const HostBox& hb, S* U, const qk_hydro_params* hp, const double* dt_dev,
+                       double dt_in, double* dt_next, hipStream_t s) {
+  qk_status st;
+  const size_t ne = (size_t)hb.elems;
+  if ((st = ensure(ctx, ctx->stage_g, 5 * ne * sizeof(S))) != QK_OK) return st;
+  if ((st = ensure(ctx, ctx->chi, ne * sizeof(R))) != QK_OK) return st;
+  S* U1 = (S*)ctx->stage_g.p;
+  R* chi = (R*)ctx->chi.p;
+  double dtv;
+  const double* dtp = resolve_dt<S>(ctx, hb, U, hp->gamma, hp->cfl, dt_dev, dt_in, &dtv, s);
+  KernelTimer& T = ctx->timer;
+  if (hb.any_fixed) launch_ghost_copy<S>(hb, U1, U, 5, s);
+  T.begin(QK_K_FLATTEN, s);
+  launch_flatten<S, R>(hb, U, chi, hp->gamma, s);
+  T.end(QK_K_FLATTEN, s);
+  T.begin(QK_K_HYDRO_STAGE, s);
+  launch_stage<S, R, 1>(hb, U, U, U1, chi, hp->gamma, dtp, dtv, nullptr, &ctx->sc->err, s);
+  T.end(QK_K_HYDRO_STAGE, s);
+  T.begin(QK_K_GHOST, s);
+  launch_ghosts<S>(hb, U1, 5, s);
+  T.end(QK_K_GHOST, s);
+  T.begin(QK_K_FLATTEN, s);
+  launch_flatten<S, R>(hb, U1, chi, hp->gamma, s);
+  T.end(QK_K_FLATTEN, s);
+  T.begin(QK_K_HYDRO_STAGE, s);
+  launch_stage<S, R, 2>(hb, U1, U, U, chi, hp->gamma, dtp, dtv, dt_next ? &ctx->sc->smax_b : nullptr,
+                        &ctx->sc->err, s);
+  T.end(QK_K_HYDRO_STAGE, s);
+  T.begin(QK_K_GHOST, s);
+  launch_ghosts<S>(hb, U, 5, s);
+  T.end(QK_K_GHOST, s);
+  if (dt_next)
+    hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(64), 0, s, &ctx->sc->smax_b, hp->cfl, hb.d.dxmin, 0.0, 0,
+                       dt_next, (int32_t*)nullptr);
+  return hip_check(ctx, hipGetLastError(), "hydro step launch");
+}
+
+qk_status read_status(qk_ctx* ctx, hipStream_t s) {
+  qk_status st = hip_check(ctx, hipStreamSynchronize(s), "stream synchronize");
+  if (st != QK_OK) return st;
+  uint32_t err = 0;
+  if ((st = hip_check(ctx, hipMemcpy(&err, &ctx->sc->err, 4, hipMemcpyDeviceToHost), "read error word")) != QK_OK)
+    return st;
+  if (err) {
+    (void)hipMemset(&ctx->sc->err, 0, 4);
+    if (err & ERR_NEG) return fail(ctx, QK_ENEGATIVE, "non-positive density, pressure or radiation energy");
+    return fail(ctx, QK_ENEWTON, "exchange solve reached its iteration cap");
+  }
+  return QK_OK;
+}
+
+}  // namespace
+
+#include "api_rad.inc"
+
+// ---------------------------------------------------------------------------
+// exported entry points
+// ---------------------------------------------------------------------------
+extern "C" {
+
+qk_status quokka_ctx_create(int device, qk_ctx** out) {
+  if (!out) return QK_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return QK_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return QK_EHIP;
+  qk_ctx* c = new qk_ctx();
+  c->device = device;
+  if (hipMalloc((void**)&c->sc, sizeof(Scalars)) != hipSuccess) {
+    delete c;
+    return QK_ENOMEM;
+  }
+  (void)hipMemset(c->sc, 0, sizeof(Scalars));
+  (void)hipDeviceSynchronize();
+  *out = c;
+  return QK_OK;
+}
+
+void quokka_ctx_destroy(qk_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  batch_cache_clear(ctx->batch);
+  for (Buf* b : {&ctx->stage_g, &ctx->stage_r, &ctx->chi})
+    if (b->p) (void)hipFree(b->p);
+  if (ctx->sc) (void)hipFree(ctx->sc);
+  delete ctx;
+}
+
+const char* quokka_last_error(const qk_ctx* ctx) { return ctx ? ctx->last_error.c_str() : "no context"; }
+
+qk_status quokka_fill_ghosts(qk_ctx* ctx, const qk_box* box, void* U, int32_t nvar, qk_precision prec,
+                             void* stream) {
+  if (!ctx) return QK_EINVAL;
+  HostBox hb;
+  qk_status st;
+  if ((st = check_box(ctx, box, hb)) != QK_OK || (st = check_prec(ctx, prec)) != QK_OK) return st;
+  if (!U || nvar < 1 || nvar > 16) return fail(ctx, QK_EINVAL, "bad state pointer or variable count");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == QK_F64)
+    launch_ghosts<double>(hb, (double*)U, nvar, s);
+  else
+    launch_ghosts<float>(hb, (float*)U, nvar, s);
+  return hip_check(ctx, hipGetLastError(), "ghost fill launch");
+}
+
+qk_status quokka_compute_dt(qk_ctx* ctx, const qk_box* box, const void* U_gas, qk_precision prec,
+                            const qk_hydro_params* hp, const qk_rad_params* rp, double* dt_dev, int32_t* nsub_dev,
+                            double* dt_host, void* stream) {
+  if (!ctx) return QK_EINVAL;
+  HostBox hb;
+  qk_status st;
+  if ((st = check_box(ctx, box, hb)) != QK_OK || (st = check_prec(ctx, prec)) != QK_OK) return st;
+  if (!U_gas) return fail(ctx, QK_EINVAL, "state pointer is NULL");
+  if (!hp && !rp) return fail(ctx, QK_EINVAL, "need hydro or radiation parameters");
+  if (hp && (st = check_hydro(ctx, hp)) != QK_OK) return st;
+  if (rp && (st = check_rad(ctx, rp)) != QK_OK) return st;
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  const double gamma = rp ? rp->gamma : hp->gamma;
+  const double cfl = hp ? hp->cfl : rp->cfl;
+  if (prec == QK_F64)
+    launch_max_signal<double>(hb, (const double*)U_gas, gamma, &ctx->sc->smax_a, &ctx->sc->err, s);
+  else
+    launch_max_signal<float>(hb, (const float*)U_gas, gamma, &ctx->sc->smax_a, &ctx->sc->err, s);
+  const double dt_r = rp ? rp->cfl * hb.d.dxmin / rp->chat : 0.0;
+  hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(64), 0, s, &ctx->sc->smax_a, cfl, hb.d.dxmin, dt_r,
+                     rp ? rp->nsub_max : 0, dt_dev ? dt_dev : &ctx->sc->dt, nsub_dev ? nsub_dev : &ctx->sc->nsub);
+  if ((st = hip_check(ctx, hipGetLastError(), "compute_dt launch")) != QK_OK) return st;
+  if (dt_host) {
+    if ((st = read_status(ctx, s)) != QK_OK) return st;
+    return hip_check(ctx, hipMemcpy(dt_host, dt_dev ? dt_dev : &ctx->sc->dt, 8, hipMemcpyDeviceToHost), "read dt");
+  }
+  return QK_OK;
+}
+
+qk_status quokka_hydro_step(qk_ctx* ctx, const qk_box* box, void* U_gas, qk_precision prec,
+                            const qk_hydro_params* hp, const double* dt_dev, double dt_in, double* dt_next_dev,
+                            void* stream) {
+  if (!ctx) return QK_EINVAL;
+  HostBox hb;
+  qk_status st;
+  if ((st = check_box(ctx, box, hb)) != QK_OK || (st = check_prec(ctx, prec)) != QK_OK ||
+      (st = check_hydro(ctx, hp)) != QK_OK)
+    return st;
+  if (!U_gas) return fail(ctx, QK_EINVAL, "state pointer is NULL");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  if (prec == QK_F64) return hydro_step_t<double, double>(ctx, hb, (double*)U_gas, hp, dt_dev, dt_in, dt_next_dev, s);
+  return hydro_step_t<float, float>(ctx, hb, (float*)U_gas, hp, dt_dev, dt_in, dt_next_dev, s);
+}
+
+qk_status quokka_sync_status(qk_ctx* ctx, void* stream) {
+  if (!ctx) return QK_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  return read_status(ctx, (hipStream_t)stream);
+}
+
+qk_status quokka_timing(qk_ctx* ctx, int32_t enable) {
+  if (!ctx) return QK_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  ctx->timer.reset();
+  ctx->timer.on = enable != 0;
+  return QK_OK;
+}
+
+qk_status quokka_kernel_time(qk_ctx* ctx, int32_t kclass, double* ms_total, int64_t* launches) {
+  if (!ctx || !ms_total || !launches || kclass < 0 || kclass >= QK_K_NCLASS) return QK_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  qk_status st = hip_check(ctx, hipDeviceSynchronize(), "synchronize");
+  if (st != QK_OK) return st;
+  double tot = 0.0;
+  int64_t n = 0;
+  for (const auto& r : ctx->timer.recs) {
+    if (r.cls != kclass) continue;
+    float ms = 0.f;
+    if ((st = hip_check(ctx, hipEventElapsedTime(&ms, r.a, r.b), "event time")) != QK_OK) return st;
+    tot += ms;
+    ++n;
+  }
+  *ms_total = tot;
+  *launches = n;
+  return QK_OK;
+}
+
+int32_t quokka_newton_iter_max(qk_ctx* ctx, void* stream) {
+  if (!ctx) return -1;
+  (void)hipSetDevice(ctx->device);
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return -1;
+  uint32_t v = 0;
+  if (hipMemcpy(&v, &ctx->sc->newton_iter_max, 4, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+  (void)hipMemset(&ctx->sc->newton_iter_max, 0, 4);
+  return (int32_t)v;
+}
+
+}  // extern "C"

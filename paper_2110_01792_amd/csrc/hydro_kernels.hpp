@@ -1,0 +1,548 @@
+// Hydrodynamics kernels of the per-cell update (gfx950, wave64).
+//
+// One SSP-RK2 stage (Section 2.2.1) is two launches:
+//   flatten_kernel : multidimensional shock-flattening coefficient chi of
+//                    every cell of the box grown by one cell (it needs the
+//                    pressure at +-3 along each axis);
+//   stage_kernel   : primitive variables, PPM along x, y, z, HLLC at every
+//                    face (each face once), unsplit divergence and the RK
+//                    combination, fused.
+// Both march in z.  A block owns a TX x TY tile of columns.  Each thread keeps
+// the primitive variables of its own column over the five planes the z sweep
+// needs in registers; the current plane, with a 3-cell halo in x and y, is
+// staged in LDS for the x and y sweeps.  Face states and fluxes of a plane
+// pass through LDS so that every interface is reconstructed and solved once.
+#pragma once
+#include "qk_device.hpp"
+
+namespace qk {
+
+template <class S, class R>
+struct StageArgs {
+  const S* Uin;          // stage input (stencil reads)
+  const S* Un;           // stage 2: U^n at the thread's own cell
+  S* Uout;               // stage 1: U^1;  stage 2: U^n (in place)
+  const R* chi;          // flattening coefficients of Uin (one variable)
+  DevBox b;
+  double gamma;
+  const double* dt_ptr;  // device dt, or NULL to use dt_val
+  double dt_val;
+  int zc;                // planes per block
+  int gx, gy;            // tiles along x and y
+  unsigned long long* smax;  // stage 2: max(|v| + c_s) of the new state (ordered bits), or NULL
+  uint32_t* err;
+};
+
+// 1-D launch: consecutive hardware blocks are dealt round-robin to the 8
+// XCDs, each with its own L2.  Re-number them so that every XCD receives one
+// contiguous range of tiles (x fastest, then y, then z chunk): neighbouring
+// tiles, which share halo planes, then run under the same L2.
+struct TileId {
+  int bx, by, bz;
+};
+__device__ __forceinline__ TileId tile_of_block(int gx, int gy) {
+  const int hw = (int)blockIdx.x, nb = (int)gridDim.x;
+  const int lg = (nb % 8 == 0) ? (hw % 8) * (nb / 8) + hw / 8 : hw;
+  TileId t;
+  t.bx = lg % gx;
+  t.by = (lg / gx) % gy;
+  t.bz = lg / (gx * gy);
+  return t;
+}
+
+template <class S>
+__device__ __forceinline__ void load_cons(const S* __restrict__ U, int64_t vs, int64_t o, double* q) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) q[v] = double(U[o + v * vs]);
+}
+
+// Block-wide maximum of a non-negative double, folded into *dst with an
+// unsigned 64-bit atomic max on its bit pattern (monotone for x >= 0).
+template <int NT>
+__device__ __forceinline__ void block_max_to(double x, unsigned long long* dst) {
+  __shared__ double red[NT / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+#pragma unroll
+    for (int k = 1; k < NT / 64; ++k) m = fmax(m, red[k]);
+    atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Flattening coefficient over cells [-1, n] in every axis.
+// ---------------------------------------------------------------------------
+template <class S, class R, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void flatten_kernel(const S* __restrict__ U, R* __restrict__ chi, DevBox b,
+                                                         double gm1, int zc, int gx, int gy) {
+  constexpr int NT = TX * TY;
+  constexpr int WX = TX + 6, WY = TY + 6;
+  __shared__ R Pp[WY][WX], uxp[WY][WX], uyp[WY][WX];
+  __shared__ R ctx[TY][TX + 2];
+  __shared__ R cty[TY + 2][TX];
+
+  const int t = threadIdx.x, tx = t % TX, ty = t / TX;
+  const TileId tl = tile_of_block(gx, gy);
+  const int xs = -1 + tl.bx * TX, ys = -1 + tl.by * TY;
+  const int tw = min(TX, b.n0 + 1 - xs), th = min(TY, b.n1 + 1 - ys);
+  const int zs = -1 + tl.bz * zc;
+  const int ze = min(zs + zc, b.n2 + 1);
+  const bool act = tx < tw && ty < th;
+  const int i = xs + tx, j = ys + ty;
+  const int64_t vs = b.vs;
+  bool bad = false;
+
+  R P[7], uz[7];  // own column, planes k-3 .. k+3
+  R cz[3];        // chi_tilde_z at k-1, k, k+1
+  auto col = [&](int kk, R& p, R& w) {
+    double q[5];
+    load_cons(U, vs, cell(b, i, j, kk), q);
+    R W[5];
+    cons_to_prim<R>(q[0], q[1], q[2], q[3], q[4], gm1, W, bad);
+    p = W[4];
+    w = W[3];
+  };
+  if (act) {
+#pragma unroll
+    for (int s = 0; s < 6; ++s) col(zs - 3 + s, P[s + 1], uz[s + 1]);
+    // window now holds planes zs-3..zs+2 in slots 1..6; compute chi_tilde_z(zs-1), (zs)
+    cz[1] = chi_tilde<R>(P[1], P[2], P[4], P[5], uz[2], uz[4]);
+    cz[2] = chi_tilde<R>(P[2], P[3], P[5], P[6], uz[3], uz[5]);
+  }
+  bad = false;  // ghost-region primitives are not checked here
+
+  for (int k = zs; k < ze; ++k) {
+    if (act) {
+#pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        P[s] = P[s + 1];
+        uz[s] = uz[s + 1];
+      }
+      col(k + 3, P[6], uz[6]);
+      cz[0] = cz[1];
+      cz[1] = cz[2];
+      cz[2] = chi_tilde<R>(P[2], P[3], P[5], P[6], uz[3], uz[5]);  // at k+1
+    }
+    // in-plane primitives over the cross-shaped region |dx| <= 3 or |dy| <= 3
+    const int ncore = tw * th, nxh = 6 * th, nyh = 6 * tw;
+    for (int it = t; it < ncore + nxh + nyh; it += NT) {
+      int xx, yy;
+      if (it < ncore) {
+        xx = it % tw;
+        yy = it / tw;
+      } else if (it < ncore + nxh) {
+        const int r = it - ncore, c = r % 6;
+        yy = r / 6;
+        xx = c < 3 ? c - 3 : tw + c - 3;
+      } else {
+        const int r = it - ncore - nxh, c = r / tw;
+        xx = r % tw;
+        yy = c < 3 ? c - 3 : th + c - 3;
+      }
+      double q[5];
+      load_cons(U, vs, cell(b, xs + xx, ys + yy, k), q);
+      R W[5];
+      cons_to_prim<R>(q[0], q[1], q[2], q[3], q[4], gm1, W, bad);
+      Pp[yy + 3][xx + 3] = W[4];
+      uxp[yy + 3][xx + 3] = W[1];
+      uyp[yy + 3][xx + 3] = W[2];
+    }
+    __syncthreads();
+    for (int it = t; it < (tw + 2) * th; it += NT) {
+      const int xx = it % (tw + 2) - 1, yy = it / (tw + 2);
+      const int X = xx + 3, Y = yy + 3;
+      ctx[yy][xx + 1] = chi_tilde<R>(Pp[Y][X - 2], Pp[Y][X - 1], Pp[Y][X + 1], Pp[Y][X + 2], uxp[Y][X - 1],
+                                     uxp[Y][X + 1]);
+    }
+    for (int it = t; it < tw * (th + 2); it += NT) {
+      const int xx = it % tw, yy = it / tw - 1;
+      const int X = xx + 3, Y = yy + 3;
+      cty[yy + 1][xx] = chi_tilde<R>(Pp[Y - 2][X], Pp[Y - 1][X], Pp[Y + 1][X], Pp[Y + 2][X], uyp[Y - 1][X],
+                                     uyp[Y + 1][X]);
+    }
+    __syncthreads();
+    if (act) {
+      const int X = tx + 3, Y = ty + 3;
+      const int sx = (Pp[Y][X + 1] - Pp[Y][X - 1] > R(0)) ? 1 : -1;
+      const int sy = (Pp[Y + 1][X] - Pp[Y - 1][X] > R(0)) ? 1 : -1;
+      const int sz = (P[4] - P[2] > R(0)) ? 1 : -1;
+      const R chx = rmin(ctx[ty][tx + 1], ctx[ty][tx + 1 + sx]);
+      const R chy = rmin(cty[ty + 1][tx], cty[ty + 1 + sy][tx]);
+      const R chz = rmin(cz[1], cz[1 + sz]);
+      chi[cell(b, i, j, k)] = rmin(chx, rmin(chy, chz));
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One SSP-RK2 stage, fused.  STAGE 1: Uout = Uin + dt L(Uin).
+// STAGE 2: Uout = 0.5 Un + 0.5 (Uin + dt L(Uin)), Uout == Un allowed (each
+// cell reads Un only at itself).
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void ppm_flat(const R* q, R chi, R& l, R& r) {
+  ppm<R>(q[0], q[1], q[2], q[3], q[4], l, r);
+  l = chi * l + (R(1) - chi) * q[2];
+  r = chi * r + (R(1) - chi) * q[2];
+}
+
+template <class S, class R, int TX, int TY, int STAGE>
+__global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs<S, R> a) {
+  constexpr int NT = TX * TY;
+  constexpr int WX = TX + 6, WY = TY + 6;
+  constexpr int NREC = ((TX + 2) * TY > TX * (TY + 2)) ? (TX + 2) * TY : TX * (TY + 2);
+  constexpr int NFL = ((TX + 1) * TY > TX * (TY + 1)) ? (TX + 1) * TY : TX * (TY + 1);
+  __shared__ R Wp[5][WY][WX];
+  __shared__ R chiP[TY + 2][TX + 2];
+  __shared__ R recL[5][NREC];
+  __shared__ R recR[5][NREC];
+  __shared__ R fl[5][NFL];
+
+  const DevBox& b = a.b;
+  const int t = threadIdx.x, tx = t % TX, ty = t / TX;
+  const TileId tl = tile_of_block(a.gx, a.gy);
+  const int x0 = tl.bx * TX, y0 = tl.by * TY;
+  const int tw = min(TX, b.n0 - x0), th = min(TY, b.n1 - y0);
+  const int z0 = tl.bz * a.zc;
+  const int z1 = min(z0 + a.zc, b.n2);
+  const bool act = tx < tw && ty < th;
+  const int i = x0 + tx, j = y0 + ty;
+  const int64_t vs = b.vs;
+  const double dt = a.dt_ptr ? *a.dt_ptr : a.dt_val;
+  const double gm1 = a.gamma - 1.0;
+  const R g = R(a.gamma);
+  const S* __restrict__ Uin = a.Uin;
+  const R* __restrict__ chi = a.chi;
+  bool bad = false;
+
+  R w[5][5];  // own column primitives: [var][plane slot], slot s = plane m-2+s
+  R aRz[5], Fz[5];
+
+  auto load_w = [&](int kk, int slot) {
+    double q[5];
+    load_cons(Uin, vs, cell(b, i, j, kk), q);
+    R W[5];
+    cons_to_prim<R>(q[0], q[1], q[2], q[3], q[4], gm1, W, bad);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) w[v][slot] = W[v];
+  };
+  auto shift_w = [&]() {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) w[v][s] = w[v][s + 1];
+    }
+  };
+  // z reconstruction of the cell centred in the window; z-rotated output
+  // (rho, w, u, v, P) so that it feeds the z Riemann problem directly
+  auto recon_z = [&](R ch, R* L, R* Rr) {
+    R l[5], r[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      R q[5] = {w[v][0], w[v][1], w[v][2], w[v][3], w[v][4]};
+      ppm_flat<R>(q, ch, l[v], r[v]);
+    }
+    L[0] = l[0]; L[1] = l[3]; L[2] = l[1]; L[3] = l[2]; L[4] = l[4];
+    Rr[0] = r[0]; Rr[1] = r[3]; Rr[2] = r[1]; Rr[3] = r[2]; Rr[4] = r[4];
+  };
+
+  if (act) {
+#pragma unroll
+    for (int s = 0; s < 5; ++s) load_w(z0 - 3 + s, s);  // centred on z0-1
+    R l[5], rprev[5];
+    recon_z(chi[cell(b, i, j, z0 - 1)], l, rprev);
+    shift_w();
+    load_w(z0 + 2, 4);  // centred on z0
+    R rcur[5];
+    recon_z(chi[cell(b, i, j, z0)], l, rcur);
+    hllc<R>(rprev, l, g, Fz);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) aRz[v] = rcur[v];
+  }
+  bad = false;
+  double smax = 0.0;
+
+  for (int k = z0; k < z1; ++k) {
+    if (act) {
+      shift_w();
+      load_w(k + 3, 4);  // window: planes k-1 .. k+3; plane k in slot 1
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Wp[v][ty + 3][tx + 3] = w[v][1];
+      chiP[ty + 1][tx + 1] = chi[cell(b, i, j, k)];
+    }
+    {
+      const int nxh = 6 * th, nyh = 6 * tw, nh = nxh + nyh;
+      const int ncx = 2 * th, ncy = 2 * tw;
+      for (int it = t; it < nh + ncx + ncy; it += NT) {
+        if (it < nh) {
+          int xx, yy;
+          if (it < nxh) {
+            const int c = it % 6;
+            yy = it / 6;
+            xx = c < 3 ? c - 3 : tw + c - 3;
+          } else {
+            const int r = it - nxh, c = r / tw;
+            xx = r % tw;
+            yy = c < 3 ? c - 3 : th + c - 3;
+          }
+          double q[5];
+          load_cons(Uin, vs, cell(b, x0 + xx, y0 + yy, k), q);
+          R W[5];
+          bool dummy = false;
+          cons_to_prim<R>(q[0], q[1], q[2], q[3], q[4], gm1, W, dummy);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) Wp[v][yy + 3][xx + 3] = W[v];
+        } else if (it < nh + ncx) {
+          const int r = it - nh;
+          const int yy = r >> 1, xx = (r & 1) ? tw : -1;
+          chiP[yy + 1][xx + 1] = chi[cell(b, x0 + xx, y0 + yy, k)];
+        } else {
+          const int r = it - nh - ncx;
+          const int xx = r % tw, yy = (r / tw) ? th : -1;
+          chiP[yy + 1][xx + 1] = chi[cell(b, x0 + xx, y0 + yy, k)];
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- x sweep: reconstruct cells -1..tw of each row, then faces
+    for (int it = t; it < (tw + 2) * th; it += NT) {
+      const int xx = it % (tw + 2) - 1, yy = it / (tw + 2);
+      const R ch = chiP[yy + 1][xx + 1];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const R* row = &Wp[v][yy + 3][xx + 1];
+        R q[5] = {row[0], row[1], row[2], row[3], row[4]};
+        ppm_flat<R>(q, ch, recL[v][it], recR[v][it]);
+      }
+    }
+    __syncthreads();
+    for (int it = t; it < (tw + 1) * th; it += NT) {
+      const int fx = it % (tw + 1), yy = it / (tw + 1);
+      const int il = yy * (tw + 2) + fx, ir = il + 1;
+      R WL[5], WR[5], F[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        WL[v] = recR[v][il];
+        WR[v] = recL[v][ir];
+      }
+      hllc<R>(WL, WR, g, F);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) fl[v][it] = F[v];
+    }
+    __syncthreads();
+    R dfx[5];
+    if (act) {
+      const int f = ty * (tw + 1) + tx;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) dfx[v] = fl[v][f + 1] - fl[v][f];
+    }
+
+    // ---- y sweep
+    for (int it = t; it < tw * (th + 2); it += NT) {
+      const int xx = it % tw, yy = it / tw - 1;
+      const R ch = chiP[yy + 1][xx + 1];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        R q[5] = {Wp[v][yy + 1][xx + 3], Wp[v][yy + 2][xx + 3], Wp[v][yy + 3][xx + 3], Wp[v][yy + 4][xx + 3],
+                  Wp[v][yy + 5][xx + 3]};
+        ppm_flat<R>(q, ch, recL[v][it], recR[v][it]);
+      }
+    }
+    __syncthreads();
+    for (int it = t; it < tw * (th + 1); it += NT) {
+      const int xx = it % tw, fy = it / tw;
+      const int il = fy * tw + xx, ir = il + tw;
+      R WL[5] = {recR[0][il], recR[2][il], recR[1][il], recR[3][il], recR[4][il]};
+      R WR[5] = {recL[0][ir], recL[2][ir], recL[1][ir], recL[3][ir], recL[4][ir]};
+      R F[5];
+      hllc<R>(WL, WR, g, F);
+      fl[0][it] = F[0];
+      fl[1][it] = F[2];
+      fl[2][it] = F[1];
+      fl[3][it] = F[3];
+      fl[4][it] = F[4];
+    }
+    __syncthreads();
+
+    if (act) {
+      R dfy[5];
+      {
+        const int f = ty * tw + tx;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) dfy[v] = fl[v][f + tw] - fl[v][f];
+      }
+      // ---- z sweep: cell k+1 is centred in the window
+      R aLn[5], aRn[5], Fk[5];
+      recon_z(chi[cell(b, i, j, k + 1)], aLn, aRn);
+      hllc<R>(aRz, aLn, g, Fk);
+      // un-rotate (rho, w, u, v, E) fluxes to (rho, x, y, z, E)
+      R Fn[5] = {Fk[0], Fk[2], Fk[3], Fk[1], Fk[4]};
+      R Fo[5] = {Fz[0], Fz[2], Fz[3], Fz[1], Fz[4]};
+      const int64_t o = cell(b, i, j, k);
+      double unew[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const double tX = double(dfx[v]) * b.inv_dx0;
+        const double tY = double(dfy[v]) * b.inv_dx1;
+        const double tZ = double(Fn[v] - Fo[v]) * b.inv_dx2;
+        const double L = -((tX + tY) + tZ);
+        const double uin = double(Uin[o + v * vs]);
+        if (STAGE == 1) {
+          unew[v] = uin + dt * L;
+        } else {
+          unew[v] = 0.5 * double(a.Un[o + v * vs]) + 0.5 * (uin + dt * L);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        a.Uout[o + v * vs] = S(unew[v]);
+        Fz[v] = Fk[v];
+        aRz[v] = aRn[v];
+      }
+      if (STAGE == 2 && a.smax) {
+        double q[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) q[v] = double(S(unew[v]));
+        const double ri = q[0];
+        const double ux = q[1] / ri, uy = q[2] / ri, uz = q[3] / ri;
+        const double ek = 0.5 * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]) / ri;
+        const double P = gm1 * (q[4] - ek);
+        const double s = sqrt((ux * ux + uy * uy) + uz * uz) + sqrt(a.gamma * P / ri);
+        smax = fmax(smax, s);
+        bad = bad || !(ri > 0.0) || !(P > 0.0);
+      }
+    }
+  }
+  if (bad) atomicOr(a.err, ERR_NEG);
+  if (STAGE == 2 && a.smax) block_max_to<NT>(smax, a.smax);
+}
+
+// ---------------------------------------------------------------------------
+// CFL reduction: max over interior cells of |v| + c_s, folded with an atomic
+// max on the ordered bit pattern.
+// ---------------------------------------------------------------------------
+template <class S, int NT>
+__global__ __launch_bounds__(NT) void max_signal_kernel(const S* __restrict__ U, DevBox b, double gamma,
+                                                        unsigned long long* smax, uint32_t* err) {
+  const int64_t ncell = (int64_t)b.n0 * b.n1 * b.n2;
+  const double gm1 = gamma - 1.0;
+  double m = 0.0;
+  bool bad = false;
+  for (int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * NT) {
+    const int i = (int)(c % b.n0);
+    const int j = (int)((c / b.n0) % b.n1);
+    const int k = (int)(c / ((int64_t)b.n0 * b.n1));
+    double q[5];
+    load_cons(U, b.vs, cell(b, i, j, k), q);
+    const double ri = q[0];
+    const double ux = q[1] / ri, uy = q[2] / ri, uz = q[3] / ri;
+    const double ek = 0.5 * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]) / ri;
+    const double P = gm1 * (q[4] - ek);
+    const double s = sqrt((ux * ux + uy * uy) + uz * uz) + sqrt(gamma * P / ri);
+    m = fmax(m, s);
+    bad = bad || !(ri > 0.0) || !(P > 0.0);
+  }
+  if (bad) atomicOr(err, ERR_NEG);
+  block_max_to<NT>(m, smax);
+}
+
+// dt = cfl * dxmin / smax; with a radiation substep limit dt_r the substep
+// count N = ceil(dt/dt_r), capped at nsub_max with dt shrunk to N dt_r.
+// Clears the accumulator for its next use.
+__global__ void finalize_dt_kernel(unsigned long long* smax_bits, double cfl, double dxmin, double dt_r,
+                                   int nsub_max, double* dt_out, int32_t* nsub_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double smax = __longlong_as_double((long long)*smax_bits);
+  double dt = cfl * dxmin / smax;
+  int n = 0;
+  if (dt_r > 0.0) {
+    const double r = ceil(dt / dt_r);
+    n = (r < 1.0) ? 1 : (r > (double)nsub_max ? nsub_max + 1 : (int)r);
+    if (n > nsub_max) {
+      n = nsub_max;
+      dt = n * dt_r;
+    }
+  }
+  if (dt_out) *dt_out = dt;
+  if (nsub_out) *nsub_out = n;
+  *smax_bits = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// Ghost fill: every ghost cell copies the cell obtained by mapping each
+// out-of-range index (periodic: wrap; outflow: clamp; fixed: itself), which is
+// the result of an x, y, z sequential fill.
+// ---------------------------------------------------------------------------
+struct GhostBC {
+  int lo[3], hi[3];
+};
+
+__device__ __forceinline__ int map_index(int i, int n, int lo, int hi) {
+  if (i < 0) return lo == 0 ? ((i % n) + n) % n : (lo == 1 ? 0 : i);
+  if (i >= n) return hi == 0 ? i % n : (hi == 1 ? n - 1 : i);
+  return i;
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void ghost_kernel(S* __restrict__ U, DevBox b, GhostBC bc, int nvar) {
+  const int ng = b.ng;
+  const int NX = b.n0 + 2 * ng, NY = b.n1 + 2 * ng;
+  const int64_t nz_slab = (int64_t)2 * ng * NY * NX;
+  const int64_t ny_slab = (int64_t)2 * ng * b.n2 * NX;
+  const int64_t nx_slab = (int64_t)2 * ng * b.n2 * b.n1;
+  const int64_t total = nz_slab + ny_slab + nx_slab;
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < total; c += (int64_t)gridDim.x * 256) {
+    int i, j, k;
+    if (c < nz_slab) {
+      i = (int)(c % NX) - ng;
+      j = (int)((c / NX) % NY) - ng;
+      const int kk = (int)(c / ((int64_t)NX * NY));
+      k = kk < ng ? kk - ng : b.n2 + (kk - ng);
+    } else if (c < nz_slab + ny_slab) {
+      const int64_t r = c - nz_slab;
+      i = (int)(r % NX) - ng;
+      const int jj = (int)((r / NX) % (2 * ng));
+      k = (int)(r / ((int64_t)NX * 2 * ng));
+      j = jj < ng ? jj - ng : b.n1 + (jj - ng);
+    } else {
+      const int64_t r = c - nz_slab - ny_slab;
+      const int ii = (int)(r % (2 * ng));
+      j = (int)((r / (2 * ng)) % b.n1);
+      k = (int)(r / ((int64_t)2 * ng * b.n1));
+      i = ii < ng ? ii - ng : b.n0 + (ii - ng);
+    }
+    const int si = map_index(i, b.n0, bc.lo[0], bc.hi[0]);
+    const int sj = map_index(j, b.n1, bc.lo[1], bc.hi[1]);
+    const int sk = map_index(k, b.n2, bc.lo[2], bc.hi[2]);
+    if (si == i && sj == j && sk == k) continue;
+    const int64_t dst = cell(b, i, j, k), src = cell(b, si, sj, sk);
+    for (int v = 0; v < nvar; ++v) U[dst + v * b.vs] = U[src + v * b.vs];
+  }
+}
+
+// Copy every ghost cell of src into dst (same layout): the stage buffer of a
+// box with fixed ghosts starts from the caller's ghost data.
+template <class S>
+__global__ __launch_bounds__(256) void ghost_copy_kernel(S* __restrict__ dst, const S* __restrict__ src, DevBox b,
+                                                         int nvar) {
+  const int ng = b.ng;
+  const int NX = b.n0 + 2 * ng, NY = b.n1 + 2 * ng, NZ = b.n2 + 2 * ng;
+  const int64_t total = (int64_t)NX * NY * NZ;
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < total; c += (int64_t)gridDim.x * 256) {
+    const int i = (int)(c % NX) - ng;
+    const int j = (int)((c / NX) % NY) - ng;
+    const int k = (int)(c / ((int64_t)NX * NY)) - ng;
+    if (i >= 0 && i < b.n0 && j >= 0 && j < b.n1 && k >= 0 && k < b.n2) continue;
+    const int64_t o = cell(b, i, j, k);
+    for (int v = 0; v < nvar; ++v) dst[o + v * b.vs] = src[o + v * b.vs];
+  }
+}
+
+}  // namespace qk

@@ -1,0 +1,177 @@
+// Device building blocks of the per-cell update (gfx950).
+//
+// Method: Wibking & Krumholz (2021), arXiv:2110.01792, Section 2.2.
+// R is the reconstruction/flux arithmetic type (double on the FP64 path,
+// float on the mixed path); anything marked "double" stays FP64 on both.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qk {
+
+enum : uint32_t { ERR_NEG = 1u, ERR_NEWTON = 2u };
+
+// Geometry of one ghosted box as seen by the kernels (element strides).
+struct DevBox {
+  int n0, n1, n2, ng;
+  int64_t py, pz, vs;
+  double inv_dx0, inv_dx1, inv_dx2;
+  double dx0, dx1, dx2, dxmin;
+};
+
+__device__ __forceinline__ int64_t cell(const DevBox& b, int i, int j, int k) {
+  return (int64_t)(k + b.ng) * b.pz + (int64_t)(j + b.ng) * b.py + (i + b.ng);
+}
+
+template <class R> __device__ __forceinline__ R rmin(R a, R b) { return fmin(a, b); }
+template <class R> __device__ __forceinline__ R rmax(R a, R b) { return fmax(a, b); }
+
+// ---------------------------------------------------------------------------
+// PPM of one cell from the five cell averages centred on it (Section 2.2.1):
+// symmetric fourth-order interface values, clamp to the neighbour range,
+// CW84 extremum test with a monotonized-central linear fallback, CW84
+// overshoot correction.  Written branch-free (selects) for SIMD execution.
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void ppm(R qm2, R qm1, R q0, R qp1, R qp2, R& aL, R& aR) {
+  const R c7 = R(7.0 / 12.0), c1 = R(1.0 / 12.0);
+  R fl = c7 * (qm1 + q0) - c1 * (qm2 + qp1);
+  R fr = c7 * (q0 + qp1) - c1 * (qm1 + qp2);
+  const R lo = rmin(qm1, rmin(q0, qp1));
+  const R hi = rmax(qm1, rmax(q0, qp1));
+  fl = rmin(rmax(fl, lo), hi);
+  fr = rmin(rmax(fr, lo), hi);
+  const R dl = q0 - qm1, dr = qp1 - q0, dc = qp1 - qm1;
+  R s = rmin(rmin(R(2) * fabs(dr), R(2) * fabs(dl)), R(0.5) * fabs(dc));
+  s = (dc < R(0)) ? -s : s;
+  s = (dr * dl > R(0)) ? s : R(0);
+  const bool ext = (fr - q0) * (q0 - fl) <= R(0);
+  const R del = fr - fl;
+  const R a6 = R(6) * (q0 - R(0.5) * (fl + fr));
+  const R da = del * a6, d2 = del * del;
+  const bool ovl = da > d2;
+  const bool ovr = !ovl && (da < -d2);
+  const R fl2 = ovl ? R(3) * q0 - R(2) * fr : fl;
+  const R fr2 = ovr ? R(3) * q0 - R(2) * fl : fr;
+  aL = ext ? q0 - R(0.5) * s : fl2;
+  aR = ext ? q0 + R(0.5) * s : fr2;
+}
+
+// ---------------------------------------------------------------------------
+// HLLC flux with PVRS wave speeds (Section 2.2.1; Toro ch. 10).  States are
+// primitive (rho, u_normal, u_t1, u_t2, P).  Output flux in the same rotated
+// order.  The two tangential speeds enter as one symmetric pair.
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ void hllc(const R* WL, const R* WR, R g, R* F) {
+  const R rL = WL[0], uL = WL[1], vL = WL[2], wL = WL[3], pL = WL[4];
+  const R rR = WR[0], uR = WR[1], vR = WR[2], wR = WR[3], pR = WR[4];
+  const R gm1 = g - R(1);
+  const R cL = sqrt(g * pL / rL);
+  const R cR = sqrt(g * pR / rR);
+  const R EL = pL / gm1 + R(0.5) * rL * (uL * uL + (vL * vL + wL * wL));
+  const R ER = pR / gm1 + R(0.5) * rR * (uR * uR + (vR * vR + wR * wR));
+  const R rbar = R(0.5) * (rL + rR);
+  const R cbar = R(0.5) * (cL + cR);
+  const R ps = rmax(R(0), R(0.5) * (pL + pR) - R(0.5) * (uR - uL) * rbar * cbar);
+  const R gq = (g + R(1)) / (R(2) * g);
+  const R qL = (ps <= pL) ? R(1) : sqrt(R(1) + gq * (ps / pL - R(1)));
+  const R qR = (ps <= pR) ? R(1) : sqrt(R(1) + gq * (ps / pR - R(1)));
+  const R SL = uL - cL * qL;
+  const R SR = uR + cR * qR;
+  const R Ss = ((pR - pL) + rL * uL * (SL - uL) - rR * uR * (SR - uR)) / (rL * (SL - uL) - rR * (SR - uR));
+  // Side and branch exactly as the four-way selection on (S_L, S*, S_R):
+  // 0 <= S_L: left flux; else 0 <= S*: left star; else 0 < S_R: right star;
+  // else right flux.  Only the chosen side's fluxes are formed.
+  const bool left = (R(0) <= SL) || (R(0) <= Ss);
+  const bool star = !(R(0) <= SL) && ((R(0) <= Ss) || (R(0) < SR));
+  const R r = left ? rL : rR, u = left ? uL : uR, v = left ? vL : vR, w = left ? wL : wR;
+  const R p = left ? pL : pR, E = left ? EL : ER, S = left ? SL : SR;
+  const R f0 = r * u, f1 = r * u * u + p, f2 = r * u * v, f3 = r * u * w, f4 = u * (E + p);
+  const R ph = (S - u) / (S - Ss);
+  const R Us0 = ph * r, Us1 = ph * (r * Ss), Us2 = ph * (r * v), Us3 = ph * (r * w);
+  const R Us4 = ph * (E + (Ss - u) * (r * Ss + p / (S - u)));
+  F[0] = star ? f0 + S * (Us0 - r) : f0;
+  F[1] = star ? f1 + S * (Us1 - r * u) : f1;
+  F[2] = star ? f2 + S * (Us2 - r * v) : f2;
+  F[3] = star ? f3 + S * (Us3 - r * w) : f3;
+  F[4] = star ? f4 + S * (Us4 - E) : f4;
+}
+
+// Conserved -> primitive.  The internal energy E - |m|^2/(2 rho) is always
+// formed in double (cancellation-prone); the rest in R.
+template <class R>
+__device__ __forceinline__ void cons_to_prim(double rho, double mx, double my, double mz, double E, double gm1,
+                                             R* W, bool& bad) {
+  const double ek = 0.5 * ((mx * mx + my * my) + mz * mz) / rho;
+  const double P = gm1 * (E - ek);
+  const R r = R(rho);
+  W[0] = r;
+  W[1] = R(mx) / r;
+  W[2] = R(my) / r;
+  W[3] = R(mz) / r;
+  W[4] = R(P);
+  bad = bad || !(rho > 0.0) || !(P > 0.0);
+}
+
+// Flattening coefficient of one cell along one axis before the neighbour
+// minimum (Miller & Colella 2002 generalising CW84; CW84 constants).
+// p* are pressures at offsets -2..+2, u* the axis velocity at -1, +1.
+template <class R>
+__device__ __forceinline__ R chi_tilde(R pm2, R pm1, R pp1, R pp2, R um1, R up1) {
+  const R dp1 = pp1 - pm1, dp2 = pp2 - pm2, du = up1 - um1;
+  const bool shock = (fabs(dp1) > R(0.33) * rmin(pp1, pm1)) && (du < R(0));
+  const R z = fabs(dp1) / rmax(fabs(dp2), R(1e-300));
+  const R t = rmin(R(1), rmax(R(0), R(1) - (z - R(0.75)) / (R(0.85) - R(0.75))));
+  return shock ? t : R(1);
+}
+
+// float cannot hold 1e-300; the floor only guards a 0/0 when both pressure
+// differences vanish, which the shock test already excludes.
+template <>
+__device__ __forceinline__ float chi_tilde<float>(float pm2, float pm1, float pp1, float pp2, float um1, float up1) {
+  const float dp1 = pp1 - pm1, dp2 = pp2 - pm2, du = up1 - um1;
+  const bool shock = (fabsf(dp1) > 0.33f * fminf(pp1, pm1)) && (du < 0.0f);
+  const float z = fabsf(dp1) / fmaxf(fabsf(dp2), 1e-30f);
+  const float t = fminf(1.0f, fmaxf(0.0f, 1.0f - (z - 0.75f) / (0.85f - 0.75f)));
+  return shock ? t : 1.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Radiation: M1 closure and HLL flux (Section 2.2.2, eq. M1_closure).
+// A face state is (E, f) with f = F/(c E); F = c E f.
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ R closure_chi(R f2, int closure) {
+  // Levermore: (3 + 4 f^2) / (5 + 2 sqrt(4 - 3 f^2)); Eddington: 1/3
+  return closure == 1 ? R(1.0 / 3.0) : (R(3) + R(4) * f2) / (R(5) + R(2) * sqrt(R(4) - R(3) * f2));
+}
+
+// Row `d` of the Eddington tensor P/E and the HLL speed factor sqrt(P_dd/E).
+// Cartesian components of f are fx, fy, fz; f itself may exceed 1 only in
+// fallback states, where the closure uses min(|f|, 1) (Section 2.2.2).
+template <class R>
+__device__ __forceinline__ void eddington_row(R fx, R fy, R fz, int d, int closure, R& Tx, R& Ty, R& Tz, R& sd) {
+  const R f2raw = (fx * fx + fy * fy) + fz * fz;
+  const R fn = sqrt(f2raw);
+  const R fh = rmin(fn, R(1));
+  const R chi = closure_chi(fh * fh, closure);
+  const R a = R(0.5) * (R(1) - chi);
+  const R bb = R(0.5) * (R(3) * chi - R(1));
+  const bool has = fn > R(0);
+  const R inv = has ? R(1) / fn : R(0);
+  const R nx = fx * inv, ny = fy * inv, nz = fz * inv;
+  const R nd = d == 0 ? nx : (d == 1 ? ny : nz);
+  const R bn = has ? bb * nd : R(0);
+  Tx = bn * nx + (d == 0 ? a : R(0));
+  Ty = bn * ny + (d == 1 ? a : R(0));
+  Tz = bn * nz + (d == 2 ? a : R(0));
+  const R Tdd = d == 0 ? Tx : (d == 1 ? Ty : Tz);
+  sd = sqrt(Tdd);
+}
+
+struct RadConst {
+  double c, chat, ratio /*chat/c*/, cc /*c*chat*/;
+};
+
+}  // namespace qk

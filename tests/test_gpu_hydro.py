@@ -1,0 +1,167 @@
+"""GPU parity of the hydrodynamics path: the HIP library (through its C ABI)
+against the FP64 oracle, element by element, on the same seeded inputs.
+Bar: relative L-infinity per variable <= 1e-10 (FP64)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_01792_amd import binding as qb
+from paper_2110_01792_amd import inputs
+from tests.gpu_util import dev, host, rel_linf, worst_cell
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = qb.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_steps(ctx, b, U, gamma, cfl, nsteps, dt=0.0):
+    Ud = dev(U)
+    ctx.fill_ghosts(b, Ud)
+    hp = qb.hydro_params(gamma, cfl)
+    for _ in range(nsteps):
+        ctx.hydro_step(b, Ud, hp, dt=dt)
+    assert ctx.sync_status() == qb.QK_OK
+    return host(Ud)
+
+
+def oracle_steps(b, U, gamma, cfl, nsteps, dt=0.0):
+    U = U.copy()
+    for _ in range(nsteps):
+        oracle.hydro_step(b, U, gamma, cfl, dt)
+    return U
+
+
+def check(g, o, b, tol=TOL, what=""):
+    e = rel_linf(g, o, b)
+    assert np.all(e <= tol), (what, e, worst_cell(g, o, b))
+
+
+@pytest.mark.parametrize("nsteps", [1, 10])
+def test_smooth_32_periodic(ctx, nsteps):
+    """32^3 periodic smooth-density workload, CFL 0.3: 1 and 10 steps."""
+    b, U, p = inputs.hydro_smooth(n=32)
+    check(gpu_steps(ctx, b, U, p["gamma"], p["cfl"], nsteps), oracle_steps(b, U, p["gamma"], p["cfl"], nsteps), b,
+          what=f"{nsteps} steps")
+
+
+@pytest.mark.parametrize("n", [(48, 48, 48), (40, 35, 27), (17, 33, 9)])
+def test_shock_ragged_tiles(ctx, n):
+    """Planar-discontinuity workload (outflow) on boxes that are not multiples of
+    the 16x16 tile or of the z chunk: ragged x/y tiles and z tails."""
+    b0, U0, p = inputs.hydro_shock(n=max(n))
+    b = inputs.make_box(n, bc=inputs.OUTFLOW)
+    U = np.zeros((5,) + b.shape)
+    g = b.ng
+    U[:, g:g + n[2], g:g + n[1], g:g + n[0]] = U0[:, g:g + n[2], g:g + n[1], g:g + n[0]]
+    check(gpu_steps(ctx, b, U, p["gamma"], p["cfl"], 2), oracle_steps(b, U, p["gamma"], p["cfl"], 2), b)
+
+
+def test_shock_256_full_size(ctx):
+    """The benchmark workload at full size (256^3 + 4 ghosts, outflow, gamma 1.4),
+    one step in the benchmark's launch configuration, compared everywhere."""
+    b, U, p = inputs.hydro_shock(n=256)
+    oracle.set_threads(0)
+    check(gpu_steps(ctx, b, U, p["gamma"], p["cfl"], 1), oracle_steps(b, U, p["gamma"], p["cfl"], 1), b)
+
+
+def test_mixed_boundaries_and_fixed_ghosts(ctx):
+    """Periodic x, outflow y, fixed z (caller ghosts held)."""
+    b0, U0, p = inputs.hydro_smooth(n=24, seed=4)
+    b = inputs.Box(b0.n, 4, b0.dx, ((0, 0), (1, 1), (2, 2)))
+    U = U0.copy()
+    oracle.fill_ghosts(inputs.Box(b0.n, 4, b0.dx, ((0, 0), (1, 1), (0, 0))), U)  # fixed z ghosts: periodic data
+    check(gpu_steps(ctx, b, U, p["gamma"], p["cfl"], 3), oracle_steps(b, U, p["gamma"], p["cfl"], 3), b)
+
+
+def test_ghost_fill_bitwise(ctx):
+    b = inputs.Box((9, 7, 5), 4, (1.0, 1.0, 1.0), ((0, 0), (1, 1), (2, 2)))
+    rng = np.random.default_rng(0)
+    U = rng.normal(size=(5,) + b.shape)
+    o = U.copy()
+    oracle.fill_ghosts(b, o)
+    Ud = dev(U)
+    ctx.fill_ghosts(b, Ud)
+    assert np.array_equal(host(Ud), o)
+
+
+def test_cfl_dt_and_fused_next_dt(ctx):
+    """compute_dt matches the oracle's CFL step; the dt fused into stage 2 equals
+    compute_dt on the new state."""
+    torch = pytest.importorskip("torch")
+    b, U, p = inputs.hydro_shock(n=40)
+    hp = qb.hydro_params(p["gamma"], p["cfl"])
+    Ud = dev(U)
+    ctx.fill_ghosts(b, Ud)
+    o = U.copy()
+    oracle.fill_ghosts(b, o)
+    dt = ctx.compute_dt(b, Ud, hp=hp)
+    dto = p["cfl"] * min(b.dx) / oracle.hydro_max_signal(b, o, p["gamma"])
+    assert abs(dt - dto) <= 1e-14 * dto
+    nxt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ctx.hydro_step(b, Ud, hp, dt=dt, dt_next_dev=nxt)
+    dt2 = ctx.compute_dt(b, Ud, hp=hp)
+    assert abs(float(nxt.item()) - dt2) <= 1e-15 * dt2
+
+
+def test_xy_swap_symmetry_bitwise(ctx):
+    """Section 3.1.8: x and y fluxes enter symmetrically; swapping the axes of
+    the input swaps the output bitwise on the GPU too."""
+    b, U, p = inputs.hydro_shock(n=32)
+    V = np.ascontiguousarray(np.swapaxes(U, 2, 3)[[0, 2, 1, 3, 4]])
+    g1 = gpu_steps(ctx, b, U, p["gamma"], p["cfl"], 3, dt=2e-3)
+    g2 = gpu_steps(ctx, b, V, p["gamma"], p["cfl"], 3, dt=2e-3)
+    assert np.array_equal(g1, np.swapaxes(g2, 2, 3)[[0, 2, 1, 3, 4]])
+
+
+def test_deterministic_and_uniform(ctx):
+    b, U, p = inputs.hydro_smooth(n=32, seed=9)
+    a1 = gpu_steps(ctx, b, U, p["gamma"], p["cfl"], 3)
+    a2 = gpu_steps(ctx, b, U, p["gamma"], p["cfl"], 3)
+    assert np.array_equal(a1, a2)
+    bu = inputs.make_box(20)
+    Uu = np.zeros((5,) + bu.shape)
+    Uu[bu.interior()] = np.array([1.3, 0.2, -0.1, 0.05, 2.7])[:, None, None, None]
+    gu = gpu_steps(ctx, bu, Uu, 1.4, 0.3, 3)
+    assert np.array_equal(gu[bu.interior()], Uu[bu.interior()])
+
+
+def test_stationary_contact_exact(ctx):
+    """Section 3.1.2 in a 3D box: a stationary contact stays exactly unchanged."""
+    b = inputs.make_box((32, 16, 16), bc=inputs.OUTFLOW)
+    U = np.zeros((5,) + b.shape)
+    x = (np.arange(32) + 0.5) / 32
+    rho = np.where(x < 0.5, 1.4, 1.0)
+    U[b.interior()] = np.stack([rho, 0 * rho, 0 * rho, 0 * rho, 0 * rho + 1.0 / 0.4])[:, None, None, :]
+    g = gpu_steps(ctx, b, U, 1.4, 0.3, 20)
+    assert np.array_equal(g[b.interior()], U[b.interior()])
+
+
+def test_argument_errors(ctx):
+    b = inputs.make_box(8)
+    torch = pytest.importorskip("torch")
+    U = torch.zeros((5,) + b.shape, dtype=torch.float64, device="cuda")
+    bad = inputs.Box(b.n, 3, b.dx, b.bc)
+    with pytest.raises(qb.QuokkaError) as e:
+        ctx.lib and ctx._ok(ctx.lib.quokka_hydro_step(ctx.h, qb.make_box(bad), qb._ptr(U), 0,
+                                                      qb.hydro_params(1.4, 0.3), None, 0.0, None, None))
+    assert e.value.status == qb.QK_EINVAL
+    half = inputs.Box(b.n, 4, b.dx, ((0, 1), (0, 0), (0, 0)))
+    with pytest.raises(qb.QuokkaError):
+        ctx._ok(ctx.lib.quokka_hydro_step(ctx.h, qb.make_box(half), qb._ptr(U), 0, qb.hydro_params(1.4, 0.3), None,
+                                          0.0, None, None))
+
+
+def test_negative_density_is_reported(ctx):
+    b, U, p = inputs.hydro_smooth(n=16)
+    U[0, 8, 8, 8] = -1.0
+    Ud = dev(U)
+    ctx.fill_ghosts(b, Ud)
+    ctx.hydro_step(b, Ud, qb.hydro_params(p["gamma"], p["cfl"]), dt=1e-4)
+    assert ctx.sync_status() == qb.QK_ENEGATIVE
+    assert ctx.sync_status() == qb.QK_OK
