@@ -57,6 +57,12 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2110_01792_amd/build.py "
                            "(or __graft_entry__.build()); there is no CPU fallback")
+    # torch ships its own HIP runtime with the same soname as the system one.
+    # Loading torch first makes the library bind to that already-loaded copy,
+    # so the process has one HIP runtime and torch's memory and streams are
+    # valid in library calls (loading the library first would bring up a
+    # second runtime, which then cannot see the device).
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, V, I32, D = ctypes.POINTER, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     sigs = {

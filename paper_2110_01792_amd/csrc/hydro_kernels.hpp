@@ -491,7 +491,7 @@ __device__ __forceinline__ int map_index(int i, int n, int lo, int hi) {
 }
 
 template <class S>
-__global__ __launch_bounds__(256) void ghost_kernel(S* __restrict__ U, DevBox b, GhostBC bc, int nvar) {
+__device__ __forceinline__ void ghost_body(S* __restrict__ U, const DevBox& b, const GhostBC& bc, int nvar) {
   const int ng = b.ng;
   const int NX = b.n0 + 2 * ng, NY = b.n1 + 2 * ng;
   const int64_t nz_slab = (int64_t)2 * ng * NY * NX;
@@ -525,6 +525,11 @@ __global__ __launch_bounds__(256) void ghost_kernel(S* __restrict__ U, DevBox b,
     const int64_t dst = cell(b, i, j, k), src = cell(b, si, sj, sk);
     for (int v = 0; v < nvar; ++v) U[dst + v * b.vs] = U[src + v * b.vs];
   }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void ghost_kernel(S* __restrict__ U, DevBox b, GhostBC bc, int nvar) {
+  ghost_body<S>(U, b, bc, nvar);
 }
 
 // Copy every ghost cell of src into dst (same layout): the stage buffer of a

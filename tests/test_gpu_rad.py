@@ -1,0 +1,179 @@
+"""GPU parity of the radiation and radiation-hydrodynamics path (HIP library
+through its C ABI) against the FP64 oracle on the same seeded inputs.
+Bar: relative L-infinity per variable <= 1e-10 (FP64)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_01792_amd import binding as qb
+from paper_2110_01792_amd import inputs
+from tests.gpu_util import dev, host, rel_linf, worst_cell
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = qb.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_rhd(ctx, b, Ug, Ur, p, nsteps=1):
+    G, R = dev(Ug), dev(Ur)
+    ctx.fill_ghosts(b, G)
+    ctx.fill_ghosts(b, R)
+    rp = qb.rad_params(p)
+    for _ in range(nsteps):
+        ctx.rhd_step(b, G, R, rp)
+    st = ctx.sync_status()
+    return host(G), host(R), st
+
+
+def oracle_rhd(b, Ug, Ur, p, nsteps=1):
+    G, R = Ug.copy(), Ur.copy()
+    for _ in range(nsteps):
+        st = oracle.rhd_step(b, G, R, p)
+    return G, R, st
+
+
+def check_pair(g, o, b, what):
+    for name, x, y in (("gas", g[0], o[0]), ("rad", g[1], o[1])):
+        e = rel_linf(x, y, b)
+        assert np.all(e <= TOL), (what, name, e, worst_cell(x, y, b))
+
+
+@pytest.mark.parametrize("n", [32, (40, 36, 20)])
+def test_rhd_small_and_ragged(ctx, n):
+    """RHD workload (log-normal density, independent gas/radiation
+    temperatures, chat = 10 max c_s): one step = hydro + 10 substeps."""
+    nn = n if isinstance(n, int) else max(n)
+    b0, Ug, Ur, p = inputs.rhd_lognormal(n=nn)
+    if not isinstance(n, int):
+        b = inputs.make_box(n)
+        g = 4
+        sl = (slice(None), slice(g, g + n[2]), slice(g, g + n[1]), slice(g, g + n[0]))
+        G0 = np.zeros((5,) + b.shape)
+        R0 = np.zeros((4,) + b.shape)
+        G0[sl] = Ug[sl]
+        R0[sl] = Ur[sl]
+        Ug, Ur = G0, R0
+    else:
+        b = b0
+    gg, gr, st = gpu_rhd(ctx, b, Ug, Ur, p, 2)
+    og, orr, ost = oracle_rhd(b, Ug, Ur, p, 2)
+    assert st == qb.QK_OK and ost["nsub"] == 10
+    check_pair((gg, gr), (og, orr), b, f"n={n}")
+
+
+def test_rhd_128(ctx):
+    """The RHD workload at 128^3, one step, compared everywhere."""
+    b, Ug, Ur, p = inputs.rhd_lognormal(n=128)
+    oracle.set_threads(0)
+    gg, gr, st = gpu_rhd(ctx, b, Ug, Ur, p, 1)
+    og, orr, _ = oracle_rhd(b, Ug, Ur, p, 1)
+    assert st == qb.QK_OK
+    check_pair((gg, gr), (og, orr), b, "128^3")
+
+
+def test_rhd_256_full_size(ctx):
+    """The RHD workload at full size (256^3), one step, compared everywhere."""
+    b, Ug, Ur, p = inputs.rhd_lognormal(n=256)
+    oracle.set_threads(0)
+    gg, gr, st = gpu_rhd(ctx, b, Ug, Ur, p, 1)
+    assert st == qb.QK_OK
+    og, orr, _ = oracle_rhd(b, Ug, Ur, p, 1)
+    check_pair((gg, gr), (og, orr), b, "256^3")
+
+
+def test_substep_count_and_dt(ctx):
+    """Section 2.2.4 substep cap: N = 10 on the RHD workload; the dt the device
+    takes equals the oracle's."""
+    torch = pytest.importorskip("torch")
+    b, Ug, Ur, p = inputs.rhd_lognormal(n=32)
+    G = dev(Ug)
+    ctx.fill_ghosts(b, G)
+    nsub = torch.zeros(1, dtype=torch.int32, device="cuda")
+    dtd = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dt = ctx.compute_dt(b, G, hp=qb.hydro_params(p["gamma"], p["cfl"]), rp=qb.rad_params(p), dt_dev=dtd,
+                        nsub_dev=nsub)
+    assert int(nsub.item()) == 10
+    og, orr, st = oracle_rhd(b, Ug, Ur, p, 1)
+    assert abs(dt - st["dt"]) <= 1e-15 * st["dt"]
+
+
+def test_optically_thick_faces_and_eddington(ctx):
+    """Optical-depth factor active (kappa large, tau_face >> 1) and the
+    Eddington closure, radiation with non-zero flux: GPU matches the oracle."""
+    b, Ug, Ur, p = inputs.rhd_lognormal(n=24, seed=13)
+    rng = np.random.default_rng(13)
+    I = b.interior()
+    Ur[(slice(1, 4),) + I[1:]] = 0.3 * p["c"] * Ur[(0,) + I[1:]] * rng.uniform(-1, 1, size=(3,) + Ur.shape[1:])[
+        (slice(None),) + I[1:]] / np.sqrt(3)
+    for closure, kap in ((0, 500.0), (1, 2.0)):
+        q = dict(p, kappa_P=kap, kappa_R=kap, closure=closure)
+        gg, gr, st = gpu_rhd(ctx, b, Ug, Ur, q, 1)
+        og, orr, _ = oracle_rhd(b, Ug, Ur, q, 1)
+        check_pair((gg, gr), (og, orr), b, f"closure={closure} kappa={kap}")
+
+
+def test_rad_step_with_host_dt_matches_oracle_substeps(ctx):
+    """quokka_rad_step with a host dt: N = ceil(dt/dt_r) substeps of transport +
+    coupling, equal to the oracle's substep sequence."""
+    b, Ug, Ur, p = inputs.rhd_lognormal(n=20, seed=21)
+    o_g, o_r = Ug.copy(), Ur.copy()
+    oracle.fill_ghosts(b, o_g)
+    oracle.fill_ghosts(b, o_r)
+    dt_r = p["cfl"] * min(b.dx) / p["chat"]
+    dt = 3.5 * dt_r
+    G, R = dev(o_g), dev(o_r)
+    ctx.rad_step(b, G, R, qb.rad_params(p), dt=dt)
+    assert ctx.sync_status() == qb.QK_OK
+    for _ in range(4):
+        oracle.rad_transport_substep(b, o_r, o_g, p, dt / 4)
+        oracle.exchange_all(b, o_g, o_r, p, dt / 4)
+        oracle.fill_ghosts(b, o_g)
+        oracle.fill_ghosts(b, o_r)
+    check_pair((host(G), host(R)), (o_g, o_r), b, "host dt")
+
+
+def test_linear_exchange_closed_form_on_gpu(ctx):
+    """Uniform box (no transport), C_v = alpha T^3: after N substeps
+    D = a_r T^4 - E_r equals D0 / (1 + lambda dt/N)^N (Section 3.2.3 set-up in
+    dimensionless form)."""
+    b = inputs.make_box(8)
+    p = inputs.rad_params(chat=50.0, eos=1, alpha_cv=4.0, kappa_P=20.0, kappa_R=20.0)
+    Ug = np.zeros((5,) + b.shape)
+    Ur = np.zeros((4,) + b.shape)
+    I = b.interior()
+    Eg0, Er0, rho = 0.5, 3.0, 1.0
+    Ug[I] = np.array([rho, 0, 0, 0, Eg0])[:, None, None, None]
+    Ur[I] = np.array([Er0, 0, 0, 0])[:, None, None, None]
+    G, R = dev(Ug), dev(Ur)
+    ctx.fill_ghosts(b, G)
+    ctx.fill_ghosts(b, R)
+    dt = 5 * p["cfl"] * min(b.dx) / p["chat"]
+    ctx.rad_step(b, G, R, qb.rad_params(p), dt=dt)
+    assert ctx.sync_status() == qb.QK_OK
+    g, r = host(G), host(R)
+    lam = rho * p["kappa_P"] * (4 * p["a_r"] * p["c"] / p["alpha_cv"] + p["chat"])
+    D0 = 4 * p["a_r"] / p["alpha_cv"] * Eg0 - Er0
+    D = 4 * p["a_r"] / p["alpha_cv"] * g[4][I[1:]] - r[0][I[1:]]
+    assert np.allclose(D, D0 / (1 + lam * dt / 5) ** 5, rtol=1e-11, atol=1e-13)
+    assert ctx.newton_iter_max() == 1
+
+
+def test_newton_failure_is_reported(ctx):
+    b, Ug, Ur, p = inputs.rhd_lognormal(n=12, seed=2)
+    q = dict(p, newton_max_iter=1, newton_tol=1e-15)
+    gg, gr, st = gpu_rhd(ctx, b, Ug, Ur, q, 1)
+    assert st == qb.QK_ENEWTON
+    assert ctx.sync_status() == qb.QK_OK
+
+
+def test_rhd_deterministic(ctx):
+    b, Ug, Ur, p = inputs.rhd_lognormal(n=32, seed=7)
+    a = gpu_rhd(ctx, b, Ug, Ur, p, 1)
+    c = gpu_rhd(ctx, b, Ug, Ur, p, 1)
+    assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
