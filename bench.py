@@ -86,6 +86,45 @@ def bench_hydro(ctx, qb, inputs, torch, steps, warmup, dtype):
     return out, b, p
 
 
+RAD_BYTES_STAGE1 = 72.0    # read E_r, F (32) + density (8), write 32   (FP64, per cell)
+RAD_BYTES_STAGE2 = 168.0   # read Ur1, Ur (64) + gas (40), write Ur (32) + m, E (32)
+
+
+def bench_rhd(ctx, qb, inputs, torch, steps, warmup, dtype, n=256):
+    b, Ug, Ur, p = inputs.rhd_lognormal(n=n)
+    G = torch.from_numpy(Ug).to(dtype).cuda()
+    R = torch.from_numpy(Ur).to(dtype).cuda()
+    del Ug, Ur
+    ctx.fill_ghosts(b, G)
+    ctx.fill_ghosts(b, R)
+    rp = qb.rad_params(p)
+    step = lambda: ctx.rhd_step(b, G, R, rp)
+    for _ in range(warmup):
+        step()
+    ms = timed_steps(step, steps, torch)
+    st = ctx.sync_status()
+    ctx.newton_iter_max()
+    ctx.timing(True)
+    for _ in range(steps):
+        step()
+    r1_ms, n1 = ctx.kernel_time(qb.K_RAD_STAGE)
+    r2_ms, n2 = ctx.kernel_time(qb.K_RAD_COUPLE)
+    hs_ms, nh = ctx.kernel_time(qb.K_HYDRO_STAGE)
+    ctx.timing(False)
+    it = ctx.newton_iter_max()
+    ncell = b.ncells
+    scale = 1.0 if dtype == torch.float64 else 0.5
+    out = {"ms_per_step": ms / steps, "cell_updates_per_s": ncell * steps / (ms * 1e-3), "status": int(st),
+           "rad_stage1_ms_avg": r1_ms / max(n1, 1), "rad_stage2_couple_ms_avg": r2_ms / max(n2, 1),
+           "hydro_stage_ms_avg": hs_ms / max(nh, 1), "launches": [n1, n2, nh], "newton_iter_max": it,
+           "ncells": ncell}
+    out["rad_stage1_achieved_GBs"] = ncell * RAD_BYTES_STAGE1 * scale / (out["rad_stage1_ms_avg"] * 1e-3) / 1e9
+    out["rad_stage2_achieved_GBs"] = ncell * RAD_BYTES_STAGE2 * scale / (out["rad_stage2_couple_ms_avg"] * 1e-3) / 1e9
+    del G, R
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline_hydro(inputs, oracle):
     b, U, p = inputs.hydro_shock(n=256)
     threads = oracle.set_threads(0)
@@ -118,6 +157,9 @@ def main():
     log("hydro FP64 256^3 ...")
     h64, b, p = bench_hydro(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float64)
     log("hydro FP64:", h64)
+    log("RHD FP64 256^3 ...")
+    r64 = bench_rhd(ctx, qb, inputs, torch, max(2, args.steps // 4), max(1, args.warmup // 2), torch.float64)
+    log("RHD FP64:", r64)
 
     roof = {
         "bound": "hbm",
@@ -148,6 +190,9 @@ def main():
                    "cells": h64["ncells"], "seed": 2},
         "roofline": roof,
         "hydro_f64": h64,
+        "rhd_f64": dict(r64, workload="RHD FP64 256^3 periodic, log-normal density, T_gas and T_rad U[0.5,2], "
+                                       "chat = 10 max c_s, kappa 1, Levermore, Newton tol 1e-12; one step = hydro "
+                                       "RK2 + 10 radiation RK2 substeps + coupling"),
     }
     if not args.no_cpu:
         import oracle

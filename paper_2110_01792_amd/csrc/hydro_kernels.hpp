@@ -476,9 +476,11 @@ __global__ void finalize_dt_kernel(unsigned long long* smax_bits, double cfl, do
 }
 
 // ---------------------------------------------------------------------------
-// Ghost fill: every ghost cell copies the cell obtained by mapping each
-// out-of-range index (periodic: wrap; outflow: clamp; fixed: itself), which is
-// the result of an x, y, z sequential fill.
+// Ghost fill with the result of an x, then y (over the full x extent), then z
+// (over the full x-y extent) sequential fill: periodic wrap, zero-gradient
+// outflow, fixed faces untouched.  Sources are never written by the same
+// launch (their first out-of-range axis in z, y, x order is a fixed face), so
+// one launch fills all ghosts without ordering.
 // ---------------------------------------------------------------------------
 struct GhostBC {
   int lo[3], hi[3];
@@ -518,9 +520,25 @@ __device__ __forceinline__ void ghost_body(S* __restrict__ U, const DevBox& b, c
       k = (int)(r / ((int64_t)2 * ng * b.n1));
       i = ii < ng ? ii - ng : b.n0 + (ii - ng);
     }
-    const int si = map_index(i, b.n0, bc.lo[0], bc.hi[0]);
-    const int sj = map_index(j, b.n1, bc.lo[1], bc.hi[1]);
-    const int sk = map_index(k, b.n2, bc.lo[2], bc.hi[2]);
+    // The x, y, z sequential fill writes a ghost cell in the fill of the last
+    // axis (in x, y, z order) along which it lies outside; a fixed face there
+    // leaves it as it is.  Its value comes from the cell mapped along that
+    // axis, which in turn was filled by the previous axes: map z, then y,
+    // then x, stopping at the first fixed face met.
+    int si = i, sj = j, sk = k;
+    bool stop = false;
+    if (k < 0 || k >= b.n2) {
+      const int kind = k < 0 ? bc.lo[2] : bc.hi[2];
+      if (kind == 2) stop = true; else sk = map_index(k, b.n2, bc.lo[2], bc.hi[2]);
+    }
+    if (!stop && (j < 0 || j >= b.n1)) {
+      const int kind = j < 0 ? bc.lo[1] : bc.hi[1];
+      if (kind == 2) stop = true; else sj = map_index(j, b.n1, bc.lo[1], bc.hi[1]);
+    }
+    if (!stop && (i < 0 || i >= b.n0)) {
+      const int kind = i < 0 ? bc.lo[0] : bc.hi[0];
+      if (kind != 2) si = map_index(i, b.n0, bc.lo[0], bc.hi[0]);
+    }
     if (si == i && sj == j && sk == k) continue;
     const int64_t dst = cell(b, i, j, k), src = cell(b, si, sj, sk);
     for (int v = 0; v < nvar; ++v) U[dst + v * b.vs] = U[src + v * b.vs];

@@ -79,8 +79,10 @@ def test_mixed_boundaries_and_fixed_ghosts(ctx):
     check(gpu_steps(ctx, b, U, p["gamma"], p["cfl"], 3), oracle_steps(b, U, p["gamma"], p["cfl"], 3), b)
 
 
-def test_ghost_fill_bitwise(ctx):
-    b = inputs.Box((9, 7, 5), 4, (1.0, 1.0, 1.0), ((0, 0), (1, 1), (2, 2)))
+@pytest.mark.parametrize("bc", [((0, 0), (1, 1), (2, 2)), ((2, 2), (0, 0), (1, 1)), ((1, 2), (2, 1), (0, 0))])
+def test_ghost_fill_bitwise(ctx, bc):
+    """Ghost fill equals the oracle's x, y, z sequential fill, fixed faces untouched."""
+    b = inputs.Box((9, 7, 5), 4, (1.0, 1.0, 1.0), bc)
     rng = np.random.default_rng(0)
     U = rng.normal(size=(5,) + b.shape)
     o = U.copy()
