@@ -236,8 +236,15 @@ template <class S, class R>
 void launch_flatten(const HostBox& hb, const S* U, R* chi, double gamma, hipStream_t s) {
   const DevBox& d = hb.d;
   Launch L = plan(d.n0 + 2, d.n1 + 2, d.n2 + 2, HTX, HTY, 2048);
-  hipLaunchKernelGGL((flatten_kernel<S, R, HTX, HTY>), dim3(L.gx * L.gy * L.gz), dim3(HTX * HTY), 0, s, U, chi, d,
-                     gamma - 1.0, L.zc, L.gx, L.gy);
+  FlatArgs<S, R> a;
+  a.U = U;
+  a.Ugh = nullptr;
+  a.chi = chi;
+  a.b = d;
+  a.gm1 = gamma - 1.0;
+  a.zc = L.zc;
+  hipLaunchKernelGGL((flatten_kernel<S, R, HTX, HTY>), dim3(L.gx * L.gy * L.gz), dim3(HTX * HTY), 0, s, a, L.gx,
+                     L.gy);
 }
 
 template <class S, class R, int STAGE>
@@ -247,6 +254,7 @@ void launch_stage(const HostBox& hb, const S* Uin, const S* Un, S* Uout, const R
   Launch L = plan(d.n0, d.n1, d.n2, HTX, HTY, 2048);
   StageArgs<S, R> a;
   a.Uin = Uin;
+  a.Ugh = nullptr;
   a.Un = Un;
   a.Uout = Uout;
   a.chi = chi;

@@ -20,6 +20,9 @@ namespace qk {
 template <class S, class R>
 struct StageArgs {
   const S* Uin;          // stage input (stencil reads)
+  const S* Ugh;          // if non-NULL: ghost cells of the stage input are read here
+                         // (boxes whose ghosts are all fixed data: the stage buffer
+                         // then needs no ghost copy)
   const S* Un;           // stage 2: U^n at the thread's own cell
   S* Uout;               // stage 1: U^1;  stage 2: U^n (in place)
   const R* chi;          // flattening coefficients of Uin (one variable)
@@ -50,6 +53,14 @@ __device__ __forceinline__ TileId tile_of_block(int gx, int gy) {
   return t;
 }
 
+// Stage input for cell (i, j, k): the ghost source for cells outside the
+// interior when one is given.
+template <class S>
+__device__ __forceinline__ const S* src_at(const S* U, const S* Ugh, const DevBox& b, int i, int j, int k) {
+  const bool out = (unsigned)i >= (unsigned)b.n0 || (unsigned)j >= (unsigned)b.n1 || (unsigned)k >= (unsigned)b.n2;
+  return (Ugh && out) ? Ugh : U;
+}
+
 template <class S>
 __device__ __forceinline__ void load_cons(const S* __restrict__ U, int64_t vs, int64_t o, double* q) {
 #pragma unroll
@@ -77,31 +88,45 @@ __device__ __forceinline__ void block_max_to(double x, unsigned long long* dst) 
 // ---------------------------------------------------------------------------
 // Flattening coefficient over cells [-1, n] in every axis.
 // ---------------------------------------------------------------------------
-template <class S, class R, int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void flatten_kernel(const S* __restrict__ U, R* __restrict__ chi, DevBox b,
-                                                         double gm1, int zc, int gx, int gy) {
-  constexpr int NT = TX * TY;
-  constexpr int WX = TX + 6, WY = TY + 6;
-  __shared__ R Pp[WY][WX], uxp[WY][WX], uyp[WY][WX];
-  __shared__ R ctx[TY][TX + 2];
-  __shared__ R cty[TY + 2][TX];
+template <class S, class R>
+struct FlatArgs {
+  const S* U;
+  const S* Ugh;  // ghost source (see StageArgs) or NULL
+  R* chi;
+  DevBox b;
+  double gm1;
+  int zc;
+};
 
+template <class R, int TX, int TY>
+struct FlatSmem {
+  R Pp[TY + 6][TX + 6], uxp[TY + 6][TX + 6], uyp[TY + 6][TX + 6];
+  R ctx[TY][TX + 2];
+  R cty[TY + 2][TX];
+};
+
+// One tile of columns (tile indices over the grown range [-1, n]).
+template <class S, class R, int TX, int TY>
+__device__ __forceinline__ void flatten_tile(const FlatArgs<S, R>& a, int tbx, int tby, int tbz,
+                                             FlatSmem<R, TX, TY>& sm) {
+  constexpr int NT = TX * TY;
+  const DevBox& b = a.b;
   const int t = threadIdx.x, tx = t % TX, ty = t / TX;
-  const TileId tl = tile_of_block(gx, gy);
-  const int xs = -1 + tl.bx * TX, ys = -1 + tl.by * TY;
+  const int xs = -1 + tbx * TX, ys = -1 + tby * TY;
   const int tw = min(TX, b.n0 + 1 - xs), th = min(TY, b.n1 + 1 - ys);
-  const int zs = -1 + tl.bz * zc;
-  const int ze = min(zs + zc, b.n2 + 1);
+  const int zs = -1 + tbz * a.zc;
+  const int ze = min(zs + a.zc, b.n2 + 1);
   const bool act = tx < tw && ty < th;
   const int i = xs + tx, j = ys + ty;
   const int64_t vs = b.vs;
+  const double gm1 = a.gm1;
   bool bad = false;
 
   R P[7], uz[7];  // own column, planes k-3 .. k+3
   R cz[3];        // chi_tilde_z at k-1, k, k+1
   auto col = [&](int kk, R& p, R& w) {
     double q[5];
-    load_cons(U, vs, cell(b, i, j, kk), q);
+    load_cons(src_at(a.U, a.Ugh, b, i, j, kk), vs, cell(b, i, j, kk), q);
     R W[5];
     cons_to_prim<R>(q[0], q[1], q[2], q[3], q[4], gm1, W, bad);
     p = W[4];
@@ -110,11 +135,10 @@ __global__ __launch_bounds__(TX* TY) void flatten_kernel(const S* __restrict__ U
   if (act) {
 #pragma unroll
     for (int s = 0; s < 6; ++s) col(zs - 3 + s, P[s + 1], uz[s + 1]);
-    // window now holds planes zs-3..zs+2 in slots 1..6; compute chi_tilde_z(zs-1), (zs)
+    // window holds planes zs-3..zs+2 in slots 1..6; chi_tilde_z(zs-1), (zs)
     cz[1] = chi_tilde<R>(P[1], P[2], P[4], P[5], uz[2], uz[4]);
     cz[2] = chi_tilde<R>(P[2], P[3], P[5], P[6], uz[3], uz[5]);
   }
-  bad = false;  // ghost-region primitives are not checked here
 
   for (int k = zs; k < ze; ++k) {
     if (act) {
@@ -145,39 +169,47 @@ __global__ __launch_bounds__(TX* TY) void flatten_kernel(const S* __restrict__ U
         yy = c < 3 ? c - 3 : th + c - 3;
       }
       double q[5];
-      load_cons(U, vs, cell(b, xs + xx, ys + yy, k), q);
+      const int gi = xs + xx, gj = ys + yy;
+      load_cons(src_at(a.U, a.Ugh, b, gi, gj, k), vs, cell(b, gi, gj, k), q);
       R W[5];
       cons_to_prim<R>(q[0], q[1], q[2], q[3], q[4], gm1, W, bad);
-      Pp[yy + 3][xx + 3] = W[4];
-      uxp[yy + 3][xx + 3] = W[1];
-      uyp[yy + 3][xx + 3] = W[2];
+      sm.Pp[yy + 3][xx + 3] = W[4];
+      sm.uxp[yy + 3][xx + 3] = W[1];
+      sm.uyp[yy + 3][xx + 3] = W[2];
     }
     __syncthreads();
     for (int it = t; it < (tw + 2) * th; it += NT) {
       const int xx = it % (tw + 2) - 1, yy = it / (tw + 2);
       const int X = xx + 3, Y = yy + 3;
-      ctx[yy][xx + 1] = chi_tilde<R>(Pp[Y][X - 2], Pp[Y][X - 1], Pp[Y][X + 1], Pp[Y][X + 2], uxp[Y][X - 1],
-                                     uxp[Y][X + 1]);
+      sm.ctx[yy][xx + 1] = chi_tilde<R>(sm.Pp[Y][X - 2], sm.Pp[Y][X - 1], sm.Pp[Y][X + 1], sm.Pp[Y][X + 2],
+                                        sm.uxp[Y][X - 1], sm.uxp[Y][X + 1]);
     }
     for (int it = t; it < tw * (th + 2); it += NT) {
       const int xx = it % tw, yy = it / tw - 1;
       const int X = xx + 3, Y = yy + 3;
-      cty[yy + 1][xx] = chi_tilde<R>(Pp[Y - 2][X], Pp[Y - 1][X], Pp[Y + 1][X], Pp[Y + 2][X], uyp[Y - 1][X],
-                                     uyp[Y + 1][X]);
+      sm.cty[yy + 1][xx] = chi_tilde<R>(sm.Pp[Y - 2][X], sm.Pp[Y - 1][X], sm.Pp[Y + 1][X], sm.Pp[Y + 2][X],
+                                        sm.uyp[Y - 1][X], sm.uyp[Y + 1][X]);
     }
     __syncthreads();
     if (act) {
       const int X = tx + 3, Y = ty + 3;
-      const int sx = (Pp[Y][X + 1] - Pp[Y][X - 1] > R(0)) ? 1 : -1;
-      const int sy = (Pp[Y + 1][X] - Pp[Y - 1][X] > R(0)) ? 1 : -1;
+      const int sx = (sm.Pp[Y][X + 1] - sm.Pp[Y][X - 1] > R(0)) ? 1 : -1;
+      const int sy = (sm.Pp[Y + 1][X] - sm.Pp[Y - 1][X] > R(0)) ? 1 : -1;
       const int sz = (P[4] - P[2] > R(0)) ? 1 : -1;
-      const R chx = rmin(ctx[ty][tx + 1], ctx[ty][tx + 1 + sx]);
-      const R chy = rmin(cty[ty + 1][tx], cty[ty + 1 + sy][tx]);
+      const R chx = rmin(sm.ctx[ty][tx + 1], sm.ctx[ty][tx + 1 + sx]);
+      const R chy = rmin(sm.cty[ty + 1][tx], sm.cty[ty + 1 + sy][tx]);
       const R chz = rmin(cz[1], cz[1 + sz]);
-      chi[cell(b, i, j, k)] = rmin(chx, rmin(chy, chz));
+      a.chi[cell(b, i, j, k)] = rmin(chx, rmin(chy, chz));
     }
     __syncthreads();
   }
+}
+
+template <class S, class R, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void flatten_kernel(FlatArgs<S, R> a, int gx, int gy) {
+  __shared__ FlatSmem<R, TX, TY> sm;
+  const TileId tl = tile_of_block(gx, gy);
+  flatten_tile<S, R, TX, TY>(a, tl.bx, tl.by, tl.bz, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -192,24 +224,34 @@ __device__ __forceinline__ void ppm_flat(const R* q, R chi, R& l, R& r) {
   r = chi * r + (R(1) - chi) * q[2];
 }
 
+template <class R, int TX, int TY>
+struct HydroSmem {
+  static constexpr int NREC = ((TX + 2) * TY > TX * (TY + 2)) ? (TX + 2) * TY : TX * (TY + 2);
+  static constexpr int NFL = ((TX + 1) * TY > TX * (TY + 1)) ? (TX + 1) * TY : TX * (TY + 1);
+  R Wp[5][TY + 6][TX + 6];
+  R chiP[TY + 2][TX + 2];
+  R recL[5][NREC];
+  R recR[5][NREC];
+  R fl[5][NFL];
+};
+
+// One tile of columns of one box: returns the thread's max(|v| + c_s) of the
+// new state (stage 2 with a.smax set), sets `bad` on a non-positive state.
 template <class S, class R, int TX, int TY, int STAGE>
-__global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs<S, R> a) {
+__device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, int tby, int tbz,
+                                             HydroSmem<R, TX, TY>& sm, bool& bad_out) {
   constexpr int NT = TX * TY;
-  constexpr int WX = TX + 6, WY = TY + 6;
-  constexpr int NREC = ((TX + 2) * TY > TX * (TY + 2)) ? (TX + 2) * TY : TX * (TY + 2);
-  constexpr int NFL = ((TX + 1) * TY > TX * (TY + 1)) ? (TX + 1) * TY : TX * (TY + 1);
-  __shared__ R Wp[5][WY][WX];
-  __shared__ R chiP[TY + 2][TX + 2];
-  __shared__ R recL[5][NREC];
-  __shared__ R recR[5][NREC];
-  __shared__ R fl[5][NFL];
+  auto& Wp = sm.Wp;
+  auto& chiP = sm.chiP;
+  auto& recL = sm.recL;
+  auto& recR = sm.recR;
+  auto& fl = sm.fl;
 
   const DevBox& b = a.b;
   const int t = threadIdx.x, tx = t % TX, ty = t / TX;
-  const TileId tl = tile_of_block(a.gx, a.gy);
-  const int x0 = tl.bx * TX, y0 = tl.by * TY;
+  const int x0 = tbx * TX, y0 = tby * TY;
   const int tw = min(TX, b.n0 - x0), th = min(TY, b.n1 - y0);
-  const int z0 = tl.bz * a.zc;
+  const int z0 = tbz * a.zc;
   const int z1 = min(z0 + a.zc, b.n2);
   const bool act = tx < tw && ty < th;
   const int i = x0 + tx, j = y0 + ty;
@@ -226,7 +268,7 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs<S, R> a) {
 
   auto load_w = [&](int kk, int slot) {
     double q[5];
-    load_cons(Uin, vs, cell(b, i, j, kk), q);
+    load_cons(src_at(Uin, a.Ugh, b, i, j, kk), vs, cell(b, i, j, kk), q);
     R W[5];
     cons_to_prim<R>(q[0], q[1], q[2], q[3], q[4], gm1, W, bad);
 #pragma unroll
@@ -292,7 +334,8 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs<S, R> a) {
             yy = c < 3 ? c - 3 : th + c - 3;
           }
           double q[5];
-          load_cons(Uin, vs, cell(b, x0 + xx, y0 + yy, k), q);
+          const int gi = x0 + xx, gj = y0 + yy;
+          load_cons(src_at(Uin, a.Ugh, b, gi, gj, k), vs, cell(b, gi, gj, k), q);
           R W[5];
           bool dummy = false;
           cons_to_prim<R>(q[0], q[1], q[2], q[3], q[4], gm1, W, dummy);
@@ -420,9 +463,20 @@ __global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs<S, R> a) {
       }
     }
   }
-  if (bad) atomicOr(a.err, ERR_NEG);
-  if (STAGE == 2 && a.smax) block_max_to<NT>(smax, a.smax);
+  bad_out = bad_out || bad;
+  return smax;
 }
+
+template <class S, class R, int TX, int TY, int STAGE>
+__global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs<S, R> a) {
+  __shared__ HydroSmem<R, TX, TY> sm;
+  const TileId tl = tile_of_block(a.gx, a.gy);
+  bool bad = false;
+  const double smax = stage_tile<S, R, TX, TY, STAGE>(a, tl.bx, tl.by, tl.bz, sm, bad);
+  if (bad) atomicOr(a.err, ERR_NEG);
+  if (STAGE == 2 && a.smax) block_max_to<TX * TY>(smax, a.smax);
+}
+
 
 // ---------------------------------------------------------------------------
 // CFL reduction: max over interior cells of |v| + c_s, folded with an atomic

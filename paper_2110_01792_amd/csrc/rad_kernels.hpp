@@ -23,6 +23,7 @@ struct RadParamsDev {
 template <class S, class R>
 struct RadStageArgs {
   const S* Uin;   // radiation stage input (4 vars)
+  const S* Ugh;   // ghost source of the stage input (all-fixed boxes) or NULL
   const S* Un;    // stage 2: radiation U^n at own cell
   S* Uout;        // stage 1: Ur1; stage 2: Ur (in place)
   S* Ug;          // gas state: density read at faces; stage 2 updates m, E
@@ -163,27 +164,34 @@ __device__ __forceinline__ void block_umax_to(uint32_t x, uint32_t* dst) {
   }
 }
 
-template <class S, class R, int TX, int TY, int STAGE>
-__global__ __launch_bounds__(TX* TY) void rad_stage_kernel(RadStageArgs<S, R> a) {
-  const int N = a.nsub_ptr ? *a.nsub_ptr : a.nsub_val;
-  if (a.sub >= N) return;  // block-uniform: the whole grid skips unused substeps
-  constexpr int NT = TX * TY;
-  constexpr int WX = TX + 6, WY = TY + 6;
-  constexpr int NREC = ((TX + 2) * TY > TX * (TY + 2)) ? (TX + 2) * TY : TX * (TY + 2);
-  constexpr int NFL = ((TX + 1) * TY > TX * (TY + 1)) ? (TX + 1) * TY : TX * (TY + 1);
-  __shared__ R Qp[4][WY][WX];
-  __shared__ R rhoP[TY + 2][TX + 2];
-  __shared__ R recL[4][NREC];
-  __shared__ R recR[4][NREC];
-  __shared__ R fl[4][NFL];
+template <class R, int TX, int TY>
+struct RadSmem {
+  static constexpr int NREC = ((TX + 2) * TY > TX * (TY + 2)) ? (TX + 2) * TY : TX * (TY + 2);
+  static constexpr int NFL = ((TX + 1) * TY > TX * (TY + 1)) ? (TX + 1) * TY : TX * (TY + 1);
+  R Qp[4][TY + 6][TX + 6];
+  R rhoP[TY + 2][TX + 2];
+  R recL[4][NREC];
+  R recR[4][NREC];
+  R fl[4][NFL];
+};
 
+// One tile of columns of one box for substep `a.sub` (the caller has checked
+// that the substep is active).  Returns the largest exchange iteration count.
+template <class S, class R, int TX, int TY, int STAGE>
+__device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tbx, int tby, int tbz, int N,
+                                             RadSmem<R, TX, TY>& sm, bool& bad_out, bool& nfail_out) {
+  constexpr int NT = TX * TY;
+  auto& Qp = sm.Qp;
+  auto& rhoP = sm.rhoP;
+  auto& recL = sm.recL;
+  auto& recR = sm.recR;
+  auto& fl = sm.fl;
   const DevBox& b = a.b;
   const RadParamsDev& p = a.p;
   const int t = threadIdx.x, tx = t % TX, ty = t / TX;
-  const TileId tl = tile_of_block(a.gx, a.gy);
-  const int x0 = tl.bx * TX, y0 = tl.by * TY;
+  const int x0 = tbx * TX, y0 = tby * TY;
   const int tw = min(TX, b.n0 - x0), th = min(TY, b.n1 - y0);
-  const int z0 = tl.bz * a.zc;
+  const int z0 = tbz * a.zc;
   const int z1 = min(z0 + a.zc, b.n2);
   const bool act = tx < tw && ty < th;
   const int i = x0 + tx, j = y0 + ty;
@@ -202,13 +210,14 @@ __global__ __launch_bounds__(TX* TY) void rad_stage_kernel(RadStageArgs<S, R> a)
 
   auto load_q = [&](int ii, int jj, int kk, R* Q, bool& flag) {
     const int64_t o = cell(b, ii, jj, kk);
-    const double E = double(Uin[o]);
+    const S* __restrict__ U = src_at(Uin, a.Ugh, b, ii, jj, kk);
+    const double E = double(U[o]);
     const R Er = R(E);
     const R inv = R(1) / (c * Er);
     Q[0] = Er;
-    Q[1] = R(Uin[o + vs]) * inv;
-    Q[2] = R(Uin[o + 2 * vs]) * inv;
-    Q[3] = R(Uin[o + 3 * vs]) * inv;
+    Q[1] = R(U[o + vs]) * inv;
+    Q[2] = R(U[o + 2 * vs]) * inv;
+    Q[3] = R(U[o + 3 * vs]) * inv;
     flag = flag || !(E > 0.0);
   };
   auto load_w = [&](int kk, int slot) {
@@ -406,11 +415,25 @@ __global__ __launch_bounds__(TX* TY) void rad_stage_kernel(RadStageArgs<S, R> a)
       bad = bad || !(un[0] > 0.0);
     }
   }
+  bad_out = bad_out || bad;
+  nfail_out = nfail_out || nfail;
+  (void)inv_c;
+  return itmax;
+}
+
+template <class S, class R, int TX, int TY, int STAGE>
+__global__ __launch_bounds__(TX* TY, 2) void rad_stage_kernel(RadStageArgs<S, R> a) {
+  const int N = a.nsub_ptr ? *a.nsub_ptr : a.nsub_val;
+  if (a.sub >= N) return;  // block-uniform: the whole grid skips unused substeps
+  __shared__ RadSmem<R, TX, TY> sm;
+  const TileId tl = tile_of_block(a.gx, a.gy);
+  bool bad = false, nfail = false;
+  const uint32_t itmax = rad_tile<S, R, TX, TY, STAGE>(a, tl.bx, tl.by, tl.bz, N, sm, bad, nfail);
   if (bad) atomicOr(a.err, ERR_NEG);
   if (nfail) atomicOr(a.err, ERR_NEWTON);
-  if (STAGE == 2) block_umax_to<NT>(itmax, a.iter_max);
-  (void)inv_c;
+  if (STAGE == 2) block_umax_to<TX * TY>(itmax, a.iter_max);
 }
+
 
 // Ghost fill guarded by the device substep count (skipped for unused substeps).
 template <class S>
