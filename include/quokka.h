@@ -150,6 +150,13 @@ qk_status quokka_batch_step(qk_ctx* ctx, const qk_box* boxes, int32_t nbox, void
                             void* const* U_rad, qk_precision prec, const qk_hydro_params* hp,
                             const qk_rad_params* rp, double* dt_host, void* stream);
 
+/* Tile edge (8 or 16 columns), z-chunk length and autotuning time (ms per
+ * candidate stage) chosen for the last batch step.  The autotuner times the
+ * side-effect-free first stages of each candidate on the caller's boxes the
+ * first time a box-shape signature is seen; results persist in the JSON file
+ * named by the environment variable QK_TUNE_CACHE, if set. */
+qk_status quokka_batch_config(qk_ctx* ctx, int32_t* tile, int32_t* zc, double* tune_ms);
+
 /* Wait for the stream, then return and clear the first sticky device error
  * (QK_ENEGATIVE, QK_ENEWTON) or QK_OK. */
 qk_status quokka_sync_status(qk_ctx* ctx, void* stream);

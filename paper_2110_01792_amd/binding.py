@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "QK_OK", 1: "QK_EINVAL", 2: "QK_ENOMEM", 3: "QK_EHIP", 4: "QK
 
 EXPORTED = ("quokka_ctx_create", "quokka_ctx_destroy", "quokka_last_error", "quokka_fill_ghosts",
             "quokka_compute_dt", "quokka_hydro_step", "quokka_rad_step", "quokka_rhd_step", "quokka_batch_step",
-            "quokka_sync_status", "quokka_newton_iter_max", "quokka_timing", "quokka_kernel_time")
+            "quokka_sync_status", "quokka_newton_iter_max", "quokka_timing", "quokka_kernel_time", "quokka_batch_config")
 K_HYDRO_STAGE, K_FLATTEN, K_RAD_STAGE, K_RAD_COUPLE, K_GHOST, K_BATCH = range(6)
 
 
@@ -81,6 +81,7 @@ def load():
         "quokka_newton_iter_max": (I32, [V, V]),
         "quokka_timing": (ctypes.c_int, [V, I32]),
         "quokka_kernel_time": (ctypes.c_int, [V, I32, P(D), P(ctypes.c_int64)]),
+        "quokka_batch_config": (ctypes.c_int, [V, P(I32), P(I32), P(D)]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -224,6 +225,12 @@ class Context:
 
     def newton_iter_max(self, stream=None):
         return self.lib.quokka_newton_iter_max(self.h, _stream(stream))
+
+    def batch_config(self):
+        """(tile, zc, tune_ms) chosen for the last batch step."""
+        t, z, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0.0)
+        self._ok(self.lib.quokka_batch_config(self.h, ctypes.byref(t), ctypes.byref(z), ctypes.byref(ms)))
+        return t.value, z.value, ms.value
 
     def timing(self, enable):
         self._ok(self.lib.quokka_timing(self.h, 1 if enable else 0))

@@ -76,6 +76,33 @@ struct KernelTimer {
   }
 };
 
+// Batched level step: graph, scratch and work lists for one box list, plus
+// the autotuned (tile, z-chunk) per box-shape signature.
+struct BatchCache {
+  uint64_t key = 0;
+  bool valid = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cs = nullptr;
+  void* pool = nullptr;
+  size_t pool_bytes = 0;
+  void* meta = nullptr;
+  size_t meta_bytes = 0;
+  int tile = 16, zc = 32;
+  double tune_ms = 0.0;
+  std::vector<std::pair<uint64_t, std::pair<int, int>>> tuned;
+  bool tune_file_read = false;
+};
+
+void batch_cache_clear(BatchCache& c) {
+  if (c.exec) (void)hipGraphExecDestroy(c.exec);
+  if (c.graph) (void)hipGraphDestroy(c.graph);
+  if (c.pool) (void)hipFree(c.pool);
+  if (c.meta) (void)hipFree(c.meta);
+  if (c.cs) (void)hipStreamDestroy(c.cs);
+  c = BatchCache();
+}
+
 struct qk_ctx {
   int device = 0;
   std::string last_error;
@@ -346,6 +373,7 @@ qk_status read_status(qk_ctx* ctx, hipStream_t s) {
 }  // namespace
 
 #include "api_rad.inc"
+#include "api_batch.inc"
 
 // ---------------------------------------------------------------------------
 // exported entry points

@@ -1,0 +1,155 @@
+"""GPU parity of the batched level step (persistent kernels over a (box,
+tile) work list, replayed as a HIP graph) against the oracle's level step."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2110_01792_amd import binding as qb
+from paper_2110_01792_amd import inputs
+from tests.gpu_util import dev, host, norm_l1, rel_linf, worst_cell
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = qb.Context(0)
+    yield c
+    c.close()
+
+
+def run_gpu(ctx, boxes, Ugs, Urs, hp, p, nsteps=1, dtype=None, check=None):
+    torch = pytest.importorskip("torch")
+    dtype = dtype or torch.float64
+    G = [dev(u, dtype) for u in Ugs]
+    R = [None if u is None else dev(u, dtype) for u in Urs]
+    rp = qb.rad_params(p)
+    dts = []
+    for s in range(nsteps):
+        dts.append(ctx.batch_step(boxes, G, R, qb.hydro_params(hp["gamma"], hp["cfl"]), rp))
+        if check is not None:
+            check(s, [host(g) for g in G], [None if r is None else host(r) for r in R])
+    assert ctx.sync_status() == qb.QK_OK
+    return [host(g) for g in G], [None if r is None else host(r) for r in R], dts
+
+
+def compare(boxes, gG, gR, oG, oR, tol=TOL, what=""):
+    for k, b in enumerate(boxes):
+        e = rel_linf(gG[k], oG[k], b)
+        assert np.all(e <= tol), (what, "gas", k, b.n, e, worst_cell(gG[k], oG[k], b))
+        if oR[k] is not None:
+            e = rel_linf(gR[k], oR[k], b)
+            assert np.all(e <= tol), (what, "rad", k, b.n, e, worst_cell(gR[k], oR[k], b))
+
+
+def test_batch_small_level_matches_oracle_over_graph_replays(ctx):
+    """12 uneven boxes (edges 8..24, half with radiation): three level steps,
+    i.e. one capture and two replays, each compared with the oracle."""
+    boxes, Ugs, Urs, p, hp = inputs.batch_level(nbox=12, seed=31, edges=(8, 16, 24))
+    oG = [u.copy() for u in Ugs]
+    oR = [None if u is None else u.copy() for u in Urs]
+    odts = []
+
+    def check(s, gG, gR):
+        st = oracle.batch_step(boxes, oG, oR, hp["gamma"], hp["cfl"], p)
+        odts.append(st["dt"])
+        compare(boxes, gG, gR, oG, oR, what=f"step {s}")
+
+    gG, gR, dts = run_gpu(ctx, boxes, Ugs, Urs, hp, p, nsteps=3, check=check)
+    for a, b in zip(dts, odts):
+        assert abs(a - b) <= 1e-14 * b
+    tile, zc, _ = ctx.batch_config()
+    assert tile in (8, 16) and zc >= 1
+
+
+def test_batch_hydro_only_equals_single_box_runs_bitwise(ctx):
+    """A batched box and the same box advanced alone with the level dt give the
+    same bits (same per-tile device code, fixed ghosts read in place)."""
+    boxes, Ugs, Urs, p, hp = inputs.batch_level(nbox=8, seed=32, edges=(8, 24, 40), rad_fraction=0.0)
+    gG, gR, dts = run_gpu(ctx, boxes, Ugs, Urs, hp, p, nsteps=1)
+    hpp = qb.hydro_params(hp["gamma"], hp["cfl"])
+    for k, b in enumerate(boxes):
+        U = dev(Ugs[k])
+        ctx.hydro_step(b, U, hpp, dt=dts[0])
+        assert np.array_equal(host(U), gG[k]), (k, b.n)
+
+
+def test_batch_full_level_sampled_against_oracle(ctx):
+    """The benchmark's batched level at full size (600 boxes, edges
+    {8..64}, half RHD): every box advanced on the GPU in one graph; a sample
+    of boxes advanced by the oracle alone with the level dt and N_sub."""
+    boxes, Ugs, Urs, p, hp = inputs.batch_level(nbox=600, seed=5)
+    gG, gR, dts = run_gpu(ctx, boxes, Ugs, Urs, hp, p, nsteps=1)
+    # level dt and substep count from the oracle's definitions
+    sig = [oracle.hydro_max_signal(b, u, p["gamma"] if r is not None else hp["gamma"])
+           for b, u, r in zip(boxes, Ugs, Urs)]
+    dt = min(hp["cfl"] * min(b.dx) / s for b, s in zip(boxes, sig))
+    dt_r = p["cfl"] * min(boxes[0].dx) / p["chat"]
+    n = int(np.ceil(dt / dt_r))
+    if n > p["nsub_max"]:
+        n, dt = p["nsub_max"], p["nsub_max"] * dt_r
+    assert abs(dts[0] - dt) <= 1e-14 * dt
+    rng = np.random.default_rng(0)
+    sample = sorted(rng.choice(len(boxes), size=12, replace=False).tolist() + [int(np.argmax(
+        [b.ncells for b in boxes]))])
+    for k in sample:
+        b, g, r = boxes[k], Ugs[k].copy(), None if Urs[k] is None else Urs[k].copy()
+        oracle.hydro_step(b, g, p["gamma"] if r is not None else hp["gamma"], hp["cfl"], dt)
+        if r is not None:
+            for _ in range(n):
+                oracle.rad_transport_substep(b, r, g, p, dt / n)
+                oracle.exchange_all(b, g, r, p, dt / n)
+        compare([b], [gG[k]], [gR[k]], [g], [r], what=f"box {k}")
+
+
+def test_batch_mixed_precision_error(ctx):
+    """FP32 state and flux arithmetic (FP64 internal energy, exchange and stage
+    sums) against the FP64 oracle started from the same FP32-rounded data."""
+    torch = pytest.importorskip("torch")
+    boxes, Ugs, Urs, p, hp = inputs.batch_level(nbox=10, seed=33, edges=(8, 16, 24))
+    Ugs = [inputs.to_f32_and_back(u) for u in Ugs]
+    Urs = [None if u is None else inputs.to_f32_and_back(u) for u in Urs]
+    gG, gR, _ = run_gpu(ctx, boxes, Ugs, Urs, hp, p, nsteps=2, dtype=torch.float32)
+    oG = [u.copy() for u in Ugs]
+    oR = [None if u is None else u.copy() for u in Urs]
+    for _ in range(2):
+        oracle.batch_step(boxes, oG, oR, hp["gamma"], hp["cfl"], p)
+    for k, b in enumerate(boxes):
+        assert np.all(norm_l1(gG[k], oG[k], b) <= 1e-5), (k, norm_l1(gG[k], oG[k], b))
+        if oR[k] is not None:
+            assert np.all(norm_l1(gR[k], oR[k], b) <= 1e-5), (k, norm_l1(gR[k], oR[k], b))
+
+
+def test_batch_autotune_cache_file(tmp_path):
+    """The autotuner writes its choice to the JSON file named by QK_TUNE_CACHE
+    and a new context reads it back."""
+    path = tmp_path / "tune.json"
+    os.environ["QK_TUNE_CACHE"] = str(path)
+    try:
+        boxes, Ugs, Urs, p, hp = inputs.batch_level(nbox=5, seed=34, edges=(8, 16))
+        c1 = qb.Context(0)
+        run_gpu(c1, boxes, Ugs, Urs, hp, p)
+        t1 = c1.batch_config()
+        c1.close()
+        data = json.loads(path.read_text())
+        assert len(data["quokka_batch_autotune"]) == 1
+        c2 = qb.Context(0)
+        run_gpu(c2, boxes, Ugs, Urs, hp, p)
+        t2 = c2.batch_config()
+        c2.close()
+        assert t1[:2] == t2[:2] and t2[2] == 0.0  # read from the file, not re-tuned
+    finally:
+        del os.environ["QK_TUNE_CACHE"]
+
+
+def test_batch_rejects_non_fixed_ghosts(ctx):
+    torch = pytest.importorskip("torch")
+    b = inputs.make_box(8)
+    U = torch.zeros((5,) + b.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(qb.QuokkaError) as e:
+        ctx.batch_step([b], [U], [None], qb.hydro_params(1.4, 0.3), None)
+    assert e.value.status == qb.QK_EINVAL
