@@ -125,6 +125,81 @@ def bench_rhd(ctx, qb, inputs, torch, steps, warmup, dtype, n=256):
     return out
 
 
+def mixed_error_hydro(ctx, qb, inputs, torch, nsteps=20):
+    """FP32 path vs FP64 path (the latter matches the oracle to 1e-10 per step)
+    on the 256^3 shock box, both from the same FP32-rounded start and the same
+    dt sequence: per-variable normalised L1 and relative L-inf."""
+    b, U, p = inputs.hydro_shock(n=256)
+    U = inputs.to_f32_and_back(U)
+    hp = qb.hydro_params(p["gamma"], p["cfl"])
+    D = torch.from_numpy(U).cuda()
+    F = D.float()
+    del U
+    ctx.fill_ghosts(b, D)
+    ctx.fill_ghosts(b, F)
+    dts = []
+    for _ in range(nsteps):
+        dts.append(ctx.compute_dt(b, D, hp=hp))
+        ctx.hydro_step(b, D, hp, dt=dts[-1])
+    for dt in dts:
+        ctx.hydro_step(b, F, hp, dt=dt)
+    torch.cuda.synchronize()
+    return error_norms(b, D, F, torch)
+
+
+def error_norms(b, D, F, torch):
+    g = b.ng
+    sl = (slice(None), slice(g, g + b.n[2]), slice(g, g + b.n[1]), slice(g, g + b.n[0]))
+    d = (F[sl].double() - D[sl]).abs().reshape(D.shape[0], -1)
+    o = D[sl].abs().reshape(D.shape[0], -1)
+    dens = D[sl][0].abs().sum()
+    l1 = (d.sum(1) / torch.where(o.sum(1) > 0, o.sum(1), dens)).cpu().tolist()
+    li = (d.max(1).values / torch.where(o.max(1).values > 0, o.max(1).values, D[sl][0].abs().max())).cpu().tolist()
+    return {"l1": l1, "linf": li}
+
+
+def mixed_error_rhd(ctx, qb, inputs, torch, nsteps=5):
+    b, Ug, Ur, p = inputs.rhd_lognormal(n=256)
+    Ug, Ur = inputs.to_f32_and_back(Ug), inputs.to_f32_and_back(Ur)
+    rp = qb.rad_params(p)
+    GD, RD = torch.from_numpy(Ug).cuda(), torch.from_numpy(Ur).cuda()
+    GF, RF = GD.float(), RD.float()
+    del Ug, Ur
+    for X in (GD, RD, GF, RF):
+        ctx.fill_ghosts(b, X)
+    for _ in range(nsteps):
+        ctx.rhd_step(b, GD, RD, rp)
+        ctx.rhd_step(b, GF, RF, rp)
+    torch.cuda.synchronize()
+    return {"gas": error_norms(b, GD, GF, torch), "rad": error_norms(b, RD, RF, torch), "steps": nsteps,
+            "note": "each path takes its own CFL dt"}
+
+
+def bench_batch(ctx, qb, inputs, torch, steps, dtype):
+    boxes, Ugs, Urs, p, hp = inputs.batch_level(nbox=600, seed=5)
+    G = [torch.from_numpy(u).to(dtype).cuda() for u in Ugs]
+    R = [None if u is None else torch.from_numpy(u).to(dtype).cuda() for u in Urs]
+    ncell = sum(b.ncells for b in boxes)
+    nrad = sum(1 for u in Urs if u is not None)
+    del Ugs, Urs
+    hpp, rp = qb.hydro_params(hp["gamma"], hp["cfl"]), qb.rad_params(p)
+    t0 = time.perf_counter()
+    ctx.batch_step(boxes, G, R, hpp, rp)  # tunes, captures, runs once
+    build_s = time.perf_counter() - t0
+    tile, zc, tune_ms = ctx.batch_config()
+    step = lambda: ctx.batch_step(boxes, G, R, hpp, rp, host_dt=False)
+    step()
+    ms = timed_steps(step, steps, torch)
+    st = ctx.sync_status()
+    del G, R
+    torch.cuda.empty_cache()
+    return {"ms_per_step": ms / steps, "cell_updates_per_s": ncell * steps / (ms * 1e-3), "status": int(st),
+            "boxes": len(boxes), "rad_boxes": nrad, "cells": ncell, "tile": tile, "zc": zc,
+            "first_call_s": build_s,
+            "workload": "600 boxes, edges per axis from {8,16,24,32,48,64}, half RHD (10 substeps), fixed ghosts; "
+                        "one graph replay per level step"}
+
+
 def cpu_baseline_hydro(inputs, oracle):
     b, U, p = inputs.hydro_shock(n=256)
     threads = oracle.set_threads(0)
@@ -160,6 +235,17 @@ def main():
     log("RHD FP64 256^3 ...")
     r64 = bench_rhd(ctx, qb, inputs, torch, max(2, args.steps // 4), max(1, args.warmup // 2), torch.float64)
     log("RHD FP64:", r64)
+    log("mixed ...")
+    h32, _, _ = bench_hydro(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float32)
+    r32 = bench_rhd(ctx, qb, inputs, torch, max(2, args.steps // 4), max(1, args.warmup // 2), torch.float32)
+    h32["error_vs_f64_20_steps"] = mixed_error_hydro(ctx, qb, inputs, torch)
+    r32["error_vs_f64"] = mixed_error_rhd(ctx, qb, inputs, torch)
+    log("mixed hydro:", h32)
+    log("mixed RHD:", r32)
+    log("batched ...")
+    b64 = bench_batch(ctx, qb, inputs, torch, max(2, args.steps // 4), torch.float64)
+    b32 = bench_batch(ctx, qb, inputs, torch, max(2, args.steps // 4), torch.float32)
+    log("batch:", b64, b32)
 
     roof = {
         "bound": "hbm",
@@ -193,6 +279,10 @@ def main():
         "rhd_f64": dict(r64, workload="RHD FP64 256^3 periodic, log-normal density, T_gas and T_rad U[0.5,2], "
                                        "chat = 10 max c_s, kappa 1, Levermore, Newton tol 1e-12; one step = hydro "
                                        "RK2 + 10 radiation RK2 substeps + coupling"),
+        "hydro_mixed": h32,
+        "rhd_mixed": r32,
+        "batch_f64": b64,
+        "batch_mixed": b32,
     }
     if not args.no_cpu:
         import oracle
