@@ -211,12 +211,39 @@ def cpu_baseline_hydro(inputs, oracle):
             "sample": "one FP64 hydro step of the full 256^3 benchmark box (%.1f s)" % t}
 
 
+def run_only(args, torch, qb, inputs):
+    """One section, printed as its own JSON line (profiling aid)."""
+    if args.only == "copy":
+        n = 2 ** 31 // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(args.warmup + args.steps):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"section": "copy", "bytes_read_per_launch": n * 8, "bytes_written_per_launch": n * 8,
+                          "launches": args.warmup + args.steps}), flush=True)
+        return
+    ctx = qb.Context(0)
+    f64, f32 = torch.float64, torch.float32
+    if args.only in ("hydro", "hydro32"):
+        out, _, _ = bench_hydro(ctx, qb, inputs, torch, args.steps, args.warmup, f64 if args.only == "hydro" else f32)
+    elif args.only in ("rhd", "rhd32"):
+        out = bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, f64 if args.only == "rhd" else f32)
+    else:
+        out = bench_batch(ctx, qb, inputs, torch, args.steps, f64)
+    ctx.close()
+    print(json.dumps({"section": args.only, **out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--only", default="all", choices=["all", "hydro", "rhd", "hydro32", "rhd32", "batch", "copy"],
+                    help="run one section only (for profiler runs); 'copy' runs a plain 2 GiB device copy used "
+                         "to calibrate the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py runs on one GPU only: the update is measured on one GPU's 256^3 share; "
@@ -228,6 +255,8 @@ def main():
     from paper_2110_01792_amd import inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.only != "all":
+        return run_only(args, torch, qb, inputs)
     ctx = qb.Context(0)
     log("hydro FP64 256^3 ...")
     h64, b, p = bench_hydro(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float64)

@@ -258,7 +258,7 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
   const int64_t vs = b.vs;
   const double dt = a.dt_ptr ? *a.dt_ptr : a.dt_val;
   const double gm1 = a.gamma - 1.0;
-  const R g = R(a.gamma);
+  const GasK<R> g = gas_k<R>(a.gamma);
   const S* __restrict__ Uin = a.Uin;
   const R* __restrict__ chi = a.chi;
   bool bad = false;

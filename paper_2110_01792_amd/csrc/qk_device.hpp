@@ -62,21 +62,34 @@ __device__ __forceinline__ void ppm(R qm2, R qm1, R q0, R qp1, R qp2, R& aL, R& 
 // primitive (rho, u_normal, u_t1, u_t2, P).  Output flux in the same rotated
 // order.  The two tangential speeds enter as one symmetric pair.
 // ---------------------------------------------------------------------------
+// Gas constants used per face, formed once per launch.
 template <class R>
-__device__ __forceinline__ void hllc(const R* WL, const R* WR, R g, R* F) {
+struct GasK {
+  R g, inv_gm1, gq;  // gamma, 1/(gamma-1), (gamma+1)/(2 gamma)
+};
+template <class R>
+__device__ __forceinline__ GasK<R> gas_k(double gamma) {
+  GasK<R> k;
+  k.g = R(gamma);
+  k.inv_gm1 = R(1.0 / (gamma - 1.0));
+  k.gq = R((gamma + 1.0) / (2.0 * gamma));
+  return k;
+}
+
+template <class R>
+__device__ __forceinline__ void hllc(const R* WL, const R* WR, const GasK<R>& k, R* F) {
   const R rL = WL[0], uL = WL[1], vL = WL[2], wL = WL[3], pL = WL[4];
   const R rR = WR[0], uR = WR[1], vR = WR[2], wR = WR[3], pR = WR[4];
-  const R gm1 = g - R(1);
+  const R g = k.g;
   const R cL = sqrt(g * pL / rL);
   const R cR = sqrt(g * pR / rR);
-  const R EL = pL / gm1 + R(0.5) * rL * (uL * uL + (vL * vL + wL * wL));
-  const R ER = pR / gm1 + R(0.5) * rR * (uR * uR + (vR * vR + wR * wR));
+  const R EL = pL * k.inv_gm1 + R(0.5) * rL * (uL * uL + (vL * vL + wL * wL));
+  const R ER = pR * k.inv_gm1 + R(0.5) * rR * (uR * uR + (vR * vR + wR * wR));
   const R rbar = R(0.5) * (rL + rR);
   const R cbar = R(0.5) * (cL + cR);
   const R ps = rmax(R(0), R(0.5) * (pL + pR) - R(0.5) * (uR - uL) * rbar * cbar);
-  const R gq = (g + R(1)) / (R(2) * g);
-  const R qL = (ps <= pL) ? R(1) : sqrt(R(1) + gq * (ps / pL - R(1)));
-  const R qR = (ps <= pR) ? R(1) : sqrt(R(1) + gq * (ps / pR - R(1)));
+  const R qL = (ps <= pL) ? R(1) : sqrt(R(1) + k.gq * (ps / pL - R(1)));
+  const R qR = (ps <= pR) ? R(1) : sqrt(R(1) + k.gq * (ps / pR - R(1)));
   const R SL = uL - cL * qL;
   const R SR = uR + cR * qR;
   const R Ss = ((pR - pL) + rL * uL * (SL - uL) - rR * uR * (SR - uR)) / (rL * (SL - uL) - rR * (SR - uR));
@@ -103,13 +116,14 @@ __device__ __forceinline__ void hllc(const R* WL, const R* WR, R g, R* F) {
 template <class R>
 __device__ __forceinline__ void cons_to_prim(double rho, double mx, double my, double mz, double E, double gm1,
                                              R* W, bool& bad) {
-  const double ek = 0.5 * ((mx * mx + my * my) + mz * mz) / rho;
+  const double inv = 1.0 / rho;
+  const double ek = 0.5 * ((mx * mx + my * my) + mz * mz) * inv;
   const double P = gm1 * (E - ek);
-  const R r = R(rho);
-  W[0] = r;
-  W[1] = R(mx) / r;
-  W[2] = R(my) / r;
-  W[3] = R(mz) / r;
+  const R ri = R(inv);
+  W[0] = R(rho);
+  W[1] = R(mx) * ri;
+  W[2] = R(my) * ri;
+  W[3] = R(mz) * ri;
   W[4] = R(P);
   bad = bad || !(rho > 0.0) || !(P > 0.0);
 }
