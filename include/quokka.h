@@ -68,8 +68,9 @@ typedef struct {
 /* Hydrodynamics (Section 2.2.1): PPM in primitive variables with
  * multidimensional shock flattening, HLLC with PVRS wave speeds, SSP-RK2. */
 typedef struct {
-  double gamma;  /* ideal-gas adiabatic index */
-  double cfl;    /* CFL number C0/D: dt = cfl * min(dx) / max(|v| + c_s) */
+  double gamma;            /* ideal-gas adiabatic index */
+  double cfl;              /* CFL number C0/D: dt = cfl * min(dx) / max(|v| + c_s) */
+  int32_t reconstruction;  /* 0 PPM (default), 1 PLM with the MC limiter (Section 2.2.1) */
 } qk_hydro_params;
 
 /* Radiation (Sections 2.1, 2.2.2, 2.2.3) under the reduced speed of light. */
@@ -86,6 +87,8 @@ typedef struct {
   int32_t closure;        /* 0 Levermore (M1), 1 Eddington (P = E/3 I)         */
   int32_t tau_correction; /* 1: scale HLL dissipation by min(1, 1/tau_face)    */
   int32_t eos;            /* 0: P = rho T, E_g = rho T/(gamma-1); 1: alpha T^4 */
+  int32_t reconstruction; /* 0 PPM, 1 PLM, for E_r and f (Section 2.2.2) and, in
+                             quokka_rhd_step, for the hydro step as well       */
 } qk_rad_params;
 
 /* Create a context on HIP device `device` (its scratch, device error word and

@@ -32,7 +32,7 @@ class _Rad(ctypes.Structure):
                 ("kappa_P", ctypes.c_double), ("kappa_R", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("alpha_cv", ctypes.c_double), ("cfl", ctypes.c_double), ("newton_tol", ctypes.c_double),
                 ("newton_max_iter", ctypes.c_int32), ("nsub_max", ctypes.c_int32), ("closure", ctypes.c_int32),
-                ("tau_correction", ctypes.c_int32), ("eos", ctypes.c_int32)]
+                ("tau_correction", ctypes.c_int32), ("eos", ctypes.c_int32), ("recon", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -55,8 +55,9 @@ def _load():
     sig = {
         "oracle_fill_ghosts": (None, [P(_Box), _D, ctypes.c_int]),
         "oracle_hydro_max_signal": (ctypes.c_double, [P(_Box), _D, ctypes.c_double]),
-        "oracle_hydro_rhs": (None, [P(_Box), _D, ctypes.c_double, _D, P(_Stats)]),
-        "oracle_hydro_step": (None, [P(_Box), _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, P(_Stats)]),
+        "oracle_hydro_rhs": (None, [P(_Box), _D, ctypes.c_double, ctypes.c_int, _D, P(_Stats)]),
+        "oracle_hydro_step": (None, [P(_Box), _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                     P(_Stats)]),
         "oracle_rad_rhs": (None, [P(_Box), _D, _D, P(_Rad), _D, P(_Stats)]),
         "oracle_rad_transport_substep": (None, [P(_Box), _D, _D, P(_Rad), ctypes.c_double, P(_Stats)]),
         "oracle_exchange_cell": (ctypes.c_int, [P(_Rad), ctypes.c_double, _D, _D, P(ctypes.c_int)]),
@@ -65,10 +66,11 @@ def _load():
                                                      ctypes.c_int64]),
         "oracle_rhd_step": (None, [P(_Box), _D, _D, P(_Rad), ctypes.c_double, P(_Stats)]),
         "oracle_batch_step": (None, [ctypes.c_int32, P(_Box), P(_D), P(_D), ctypes.c_double, ctypes.c_double,
-                                     P(_Rad), P(_Stats)]),
+                                     ctypes.c_int, P(_Rad), P(_Stats)]),
         "oracle_closure_chi": (ctypes.c_double, [ctypes.c_double, ctypes.c_int]),
         "oracle_closure_pressure": (None, [ctypes.c_double, _D, ctypes.c_double, ctypes.c_int, _D]),
         "oracle_ppm_cell": (None, [_D, _D]),
+        "oracle_plm_cell": (None, [_D, _D]),
         "oracle_hllc": (None, [_D, _D, ctypes.c_double, _D]),
         "oracle_hll_rad": (None, [ctypes.c_double, _D, ctypes.c_double, _D, ctypes.c_int, P(_Rad),
                                   ctypes.c_double, _D]),
@@ -99,6 +101,7 @@ def _rad(p):
         setattr(r, k, float(p[k]))
     for k in ("newton_max_iter", "nsub_max", "closure", "tau_correction", "eos"):
         setattr(r, k, int(p[k]))
+    r.recon = int(p.get("recon", 0))
     return r
 
 
@@ -133,20 +136,21 @@ def hydro_max_signal(b, U, gamma):
     return _load().oracle_hydro_max_signal(ctypes.byref(_box(b)), _ptr(U), float(gamma))
 
 
-def hydro_rhs(b, U, gamma):
-    """L(U) of the hydrodynamic subsystem over interior cells (ghosts of U must be filled)."""
+def hydro_rhs(b, U, gamma, recon=0):
+    """L(U) of the hydrodynamic subsystem over interior cells (ghosts of U must be filled).
+    recon: 0 PPM, 1 PLM."""
     _check(b, U, 5)
     L = np.zeros_like(U)
     st = _Stats()
-    _load().oracle_hydro_rhs(ctypes.byref(_box(b)), _ptr(U), float(gamma), _ptr(L), ctypes.byref(st))
+    _load().oracle_hydro_rhs(ctypes.byref(_box(b)), _ptr(U), float(gamma), int(recon), _ptr(L), ctypes.byref(st))
     return L, _stats(st)
 
 
-def hydro_step(b, U, gamma, cfl, dt=0.0):
-    """One SSP-RK2 hydro step in place; dt <= 0 takes the CFL step."""
+def hydro_step(b, U, gamma, cfl, dt=0.0, recon=0):
+    """One SSP-RK2 hydro step in place; dt <= 0 takes the CFL step; recon: 0 PPM, 1 PLM."""
     _check(b, U, 5)
     st = _Stats()
-    _load().oracle_hydro_step(ctypes.byref(_box(b)), _ptr(U), float(gamma), float(cfl), float(dt),
+    _load().oracle_hydro_step(ctypes.byref(_box(b)), _ptr(U), float(gamma), float(cfl), float(dt), int(recon),
                               ctypes.byref(st))
     return _stats(st)
 
@@ -206,14 +210,14 @@ def rhd_step(b, Ug, Ur, p, dt=0.0):
     return _stats(st)
 
 
-def batch_step(boxes, Ugs, Urs, gamma_h, cfl, p):
+def batch_step(boxes, Ugs, Urs, gamma_h, cfl, p, recon_h=0):
     """One level step over boxes with fixed ghosts; Urs[i] None marks a hydro-only box."""
     nb = len(boxes)
     cboxes = (_Box * nb)(*[_box(b) for b in boxes])
     gp = (_D * nb)(*[_ptr(u) for u in Ugs])
     rp = (_D * nb)(*[(_ptr(u) if u is not None else ctypes.cast(None, _D)) for u in Urs])
     st = _Stats()
-    _load().oracle_batch_step(nb, cboxes, gp, rp, float(gamma_h), float(cfl), ctypes.byref(_rad(p)),
+    _load().oracle_batch_step(nb, cboxes, gp, rp, float(gamma_h), float(cfl), int(recon_h), ctypes.byref(_rad(p)),
                               ctypes.byref(st))
     return _stats(st)
 
@@ -227,6 +231,13 @@ def closure_pressure(E, F, c, closure=0):
     P = np.zeros(9)
     _load().oracle_closure_pressure(float(E), _ptr(Fa), float(c), int(closure), _ptr(P))
     return P.reshape(3, 3)
+
+
+def plm_cell(q3):
+    q = np.ascontiguousarray(q3, dtype=np.float64)
+    out = np.zeros(2)
+    _load().oracle_plm_cell(_ptr(q), _ptr(out))
+    return out[0], out[1]
 
 
 def ppm_cell(q5):

@@ -4,7 +4,7 @@
  * library is checked against.  It shares no code with the GPU path.
  *
  * Every stage is written as whole-array passes in the order the paper gives:
- * conserved -> primitive, shock flattening, PPM per direction, Riemann flux
+ * conserved -> primitive, shock flattening, PPM (or PLM) per direction, Riemann flux
  * per face, unsplit divergence, SSP-RK2 combination.  No blocking, fusion or
  * reordering.  Compile with -O2 -ffp-contract=off -fno-fast-math.
  *
@@ -162,6 +162,30 @@ static void ppm(double qm2, double qm1, double q0, double qp1, double qp2, doubl
 
 void oracle_ppm_cell(const double q[5], double out[2]) { ppm(q[0], q[1], q[2], q[3], q[4], &out[0], &out[1]); }
 
+/* PLM with the monotonized-central slope limiter (Section 2.2.1, the
+ * compile-time alternative to PPM; van Leer 1977): slope 0 at an extremum of
+ * the cell averages, else sign(dc) min(2|dr|, 2|dl|, |dc|/2); interface values
+ * q -+ slope/2. */
+static void plm(double qm1, double q0, double qp1, double* aL, double* aR) {
+  const double dl = q0 - qm1, dr = qp1 - q0, dc = qp1 - qm1;
+  double s = 0.0;
+  if (dr * dl > 0.0) {
+    s = fmin(fmin(2.0 * fabs(dr), 2.0 * fabs(dl)), 0.5 * fabs(dc));
+    if (dc < 0.0) s = -s;
+  }
+  *aL = q0 - 0.5 * s;
+  *aR = q0 + 0.5 * s;
+}
+
+void oracle_plm_cell(const double q[3], double out[2]) { plm(q[0], q[1], q[2], &out[0], &out[1]); }
+
+static void reconstruct(int recon, const double* q, size_t o, ptrdiff_t s, double* l, double* r) {
+  if (recon == 1)
+    plm(q[o - s], q[o], q[o + s], l, r);
+  else
+    ppm(q[o - 2 * s], q[o - s], q[o], q[o + s], q[o + 2 * s], l, r);
+}
+
 /* ------------------------------------------------------------------------ */
 /* HLLC flux with PVRS wave-speed estimates (Section 2.2.1, Riemann solver   */
 /* paragraph; Toro 2013 ch. 10).  States are primitive and rotated so that   */
@@ -240,7 +264,7 @@ static double chi_tilde(const double* P, const double* u, size_t o, ptrdiff_t s)
     for (int j = (J0); j < (J1); ++j)                               \
       for (int i = (I0); i < (I1); ++i)
 
-void oracle_hydro_rhs(const ob_box* b, const double* U, double gam, double* L, ob_stats* st) {
+void oracle_hydro_rhs(const ob_box* b, const double* U, double gam, int recon, double* L, ob_stats* st) {
   geo g = make_geo(b);
   const size_t vs = g.vs;
   double* W = (double*)malloc(5 * vs * sizeof(double));
@@ -316,7 +340,7 @@ void oracle_hydro_rhs(const ob_box* b, const double* U, double gam, double* L, o
       for (int v = 0; v < 5; ++v) {
         const double* q = W + v * vs;
         double l, r;
-        ppm(q[o - 2 * s], q[o - s], q[o], q[o + s], q[o + 2 * s], &l, &r);
+        reconstruct(recon, q, o, s, &l, &r);
         aL[v * vs + o] = x * l + (1.0 - x) * q[o];
         aR[v * vs + o] = x * r + (1.0 - x) * q[o];
       }
@@ -417,27 +441,27 @@ static void euler_interior(const geo* g, int nvar, const double* Un, double* U1,
   }
 }
 
-static void hydro_rk2(const ob_box* b, double* U, double gam, double dt, ob_stats* st) {
+static void hydro_rk2(const ob_box* b, double* U, double gam, double dt, int recon, ob_stats* st) {
   geo g = make_geo(b);
   const size_t nb = 5 * g.vs * sizeof(double);
   double* U1 = (double*)malloc(nb);
   double* Lb = (double*)calloc(5 * g.vs, sizeof(double));
   memcpy(U1, U, nb); /* fixed ghosts of the stage state equal those of U */
-  oracle_hydro_rhs(b, U, gam, Lb, st);
+  oracle_hydro_rhs(b, U, gam, recon, Lb, st);
   euler_interior(&g, 5, U, U1, Lb, dt);
   oracle_fill_ghosts(b, U1, 5);
-  oracle_hydro_rhs(b, U1, gam, Lb, st);
+  oracle_hydro_rhs(b, U1, gam, recon, Lb, st);
   rk2_interior(&g, 5, U, U1, Lb, dt);
   oracle_fill_ghosts(b, U, 5);
   free(U1);
   free(Lb);
 }
 
-void oracle_hydro_step(const ob_box* b, double* U, double gam, double cfl, double dt_in, ob_stats* st) {
+void oracle_hydro_step(const ob_box* b, double* U, double gam, double cfl, double dt_in, int recon, ob_stats* st) {
   oracle_fill_ghosts(b, U, 5);
   double dt = dt_in;
   if (!(dt > 0.0)) dt = cfl * dx_min(b) / oracle_hydro_max_signal(b, U, gam);
-  hydro_rk2(b, U, gam, dt, st);
+  hydro_rk2(b, U, gam, dt, recon, st);
   if (st) {
     st->dt = dt;
     st->nsub = 0;
@@ -527,7 +551,7 @@ void oracle_rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const o
       const size_t o = IX(&g, i, j, k);
       for (int v = 0; v < 4; ++v) {
         const double* q = Q + v * vs;
-        ppm(q[o - 2 * s], q[o - s], q[o], q[o + s], q[o + 2 * s], &aL[v * vs + o], &aR[v * vs + o]);
+        reconstruct(p->recon, q, o, s, &aL[v * vs + o], &aR[v * vs + o]);
       }
     }
     int lo2[3] = {0, 0, 0}, hi2[3] = {g.n[0], g.n[1], g.n[2]};
@@ -748,7 +772,7 @@ void oracle_rhd_step(const ob_box* b, double* Ug, double* Ur, const ob_rad* p, d
   const double dt_r = p->cfl * dx_min(b) / p->chat;
   const int N = nsub_for(&dt_h, dt_r, p->nsub_max);
   const double dts = dt_h / N;
-  hydro_rk2(b, Ug, p->gamma, dt_h, st);
+  hydro_rk2(b, Ug, p->gamma, dt_h, p->recon, st);
   for (int s = 0; s < N; ++s) {
     oracle_rad_transport_substep(b, Ur, Ug, p, dts, st);
     oracle_exchange_all(b, Ug, Ur, p, dts, st);
@@ -766,7 +790,7 @@ void oracle_rhd_step(const ob_box* b, double* Ug, double* Ur, const ob_rad* p, d
  * count from chat, every box advanced with them.  Ur[i] == NULL marks a
  * hydro-only box. */
 void oracle_batch_step(int32_t nbox, const ob_box* boxes, double* const* Ug, double* const* Ur, double gamma_h,
-                       double cfl, const ob_rad* p, ob_stats* st) {
+                       double cfl, int recon_h, const ob_rad* p, ob_stats* st) {
   double dt_h = INFINITY, dxm = INFINITY;
   int any_rad = 0;
   for (int i = 0; i < nbox; ++i) {
@@ -782,7 +806,7 @@ void oracle_batch_step(int32_t nbox, const ob_box* boxes, double* const* Ug, dou
   if (any_rad) N = nsub_for(&dt_h, cfl * dxm / p->chat, p->nsub_max);
   for (int i = 0; i < nbox; ++i) {
     const double gam = Ur[i] ? p->gamma : gamma_h;
-    hydro_rk2(&boxes[i], Ug[i], gam, dt_h, st);
+    hydro_rk2(&boxes[i], Ug[i], gam, dt_h, Ur[i] ? p->recon : recon_h, st);
     if (!Ur[i]) continue;
     for (int s = 0; s < N; ++s) {
       oracle_rad_transport_substep(&boxes[i], Ur[i], Ug[i], p, dt_h / N, st);

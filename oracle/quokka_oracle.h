@@ -32,9 +32,9 @@ typedef struct {
 
 typedef struct {
   double c, chat, a_r, kappa_P, kappa_R, gamma, alpha_cv, cfl, newton_tol;
-  int32_t newton_max_iter, nsub_max, closure, tau_correction, eos;
+  int32_t newton_max_iter, nsub_max, closure, tau_correction, eos, recon;
 } ob_rad;   /* closure: 0 Levermore, 1 Eddington.  eos: 0 ideal (P = rho T),
-               1 E_g = alpha T^4 / 4. */
+               1 E_g = alpha T^4 / 4.  recon: 0 PPM, 1 PLM (hydro and radiation). */
 
 /* Result counters returned by the step drivers. */
 typedef struct {
@@ -47,8 +47,9 @@ typedef struct {
 
 void   oracle_fill_ghosts(const ob_box* b, double* U, int nvar);
 double oracle_hydro_max_signal(const ob_box* b, const double* U, double gamma);
-void   oracle_hydro_rhs(const ob_box* b, const double* U, double gamma, double* L, ob_stats* st);
-void   oracle_hydro_step(const ob_box* b, double* U, double gamma, double cfl, double dt_in, ob_stats* st);
+void   oracle_hydro_rhs(const ob_box* b, const double* U, double gamma, int recon, double* L, ob_stats* st);
+void   oracle_hydro_step(const ob_box* b, double* U, double gamma, double cfl, double dt_in, int recon,
+                         ob_stats* st);
 void   oracle_rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const ob_rad* p, double* L, ob_stats* st);
 void   oracle_rad_transport_substep(const ob_box* b, double* Ur, const double* Ug, const ob_rad* p, double dt, ob_stats* st);
 int    oracle_exchange_cell(const ob_rad* p, double dt, double* rho_m_E /*5*/, double* Er_F /*4*/, int* iters);
@@ -57,10 +58,11 @@ double oracle_exchange_series(const ob_rad* p, double dt, int64_t nsteps, double
                               double* T4_out, int64_t every);
 void   oracle_rhd_step(const ob_box* b, double* Ug, double* Ur, const ob_rad* p, double dt_in, ob_stats* st);
 void   oracle_batch_step(int32_t nbox, const ob_box* boxes, double* const* Ug, double* const* Ur,
-                         double gamma_h, double cfl, const ob_rad* p, ob_stats* st);
+                         double gamma_h, double cfl, int recon_h, const ob_rad* p, ob_stats* st);
 double oracle_closure_chi(double fhat, int closure);
 void   oracle_closure_pressure(double E, const double F[3], double c, int closure, double P[9]);
 void   oracle_ppm_cell(const double q[5], double out_aL_aR[2]);
+void   oracle_plm_cell(const double q[3], double out_aL_aR[2]);
 void   oracle_hllc(const double WL[5], const double WR[5], double gamma, double flux[5]);
 void   oracle_hll_rad(double EL, const double FL[3], double ER, const double FR[3], int dir,
                       const ob_rad* p, double eps, double flux[4]);

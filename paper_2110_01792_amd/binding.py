@@ -29,7 +29,7 @@ class QkBox(ctypes.Structure):
 
 
 class QkHydroParams(ctypes.Structure):
-    _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double)]
+    _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double), ("reconstruction", ctypes.c_int32)]
 
 
 class QkRadParams(ctypes.Structure):
@@ -37,7 +37,7 @@ class QkRadParams(ctypes.Structure):
                 ("kappa_P", ctypes.c_double), ("kappa_R", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("alpha_cv", ctypes.c_double), ("cfl", ctypes.c_double), ("newton_tol", ctypes.c_double),
                 ("newton_max_iter", ctypes.c_int32), ("nsub_max", ctypes.c_int32), ("closure", ctypes.c_int32),
-                ("tau_correction", ctypes.c_int32), ("eos", ctypes.c_int32)]
+                ("tau_correction", ctypes.c_int32), ("eos", ctypes.c_int32), ("reconstruction", ctypes.c_int32)]
 
 
 class QuokkaError(RuntimeError):
@@ -104,8 +104,9 @@ def make_box(b):
     return q
 
 
-def hydro_params(gamma, cfl):
-    return QkHydroParams(float(gamma), float(cfl))
+def hydro_params(gamma, cfl, recon=0):
+    """recon: 0 PPM, 1 PLM."""
+    return QkHydroParams(float(gamma), float(cfl), int(recon))
 
 
 def rad_params(p):
@@ -114,6 +115,7 @@ def rad_params(p):
         setattr(r, k, float(p[k]))
     for k in ("newton_max_iter", "nsub_max", "closure", "tau_correction", "eos"):
         setattr(r, k, int(p[k]))
+    r.reconstruction = int(p.get("recon", 0))
     return r
 
 

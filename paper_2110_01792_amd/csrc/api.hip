@@ -193,6 +193,7 @@ qk_status check_prec(qk_ctx* ctx, qk_precision p) {
 qk_status check_hydro(qk_ctx* ctx, const qk_hydro_params* hp) {
   if (!hp) return fail(ctx, QK_EINVAL, "hydro params NULL");
   if (!(hp->gamma > 1.0) || !(hp->cfl > 0.0)) return fail(ctx, QK_EINVAL, "need gamma > 1 and cfl > 0");
+  if (hp->reconstruction < 0 || hp->reconstruction > 1) return fail(ctx, QK_EINVAL, "unknown reconstruction");
   return QK_OK;
 }
 
@@ -201,7 +202,7 @@ qk_status check_rad(qk_ctx* ctx, const qk_rad_params* rp) {
   if (!(rp->c > 0) || !(rp->chat > 0) || !(rp->a_r > 0) || !(rp->gamma > 1.0) || !(rp->cfl > 0) ||
       !(rp->newton_tol > 0) || rp->newton_max_iter < 1 || rp->nsub_max < 1 || rp->closure < 0 ||
       rp->closure > 1 || rp->eos < 0 || rp->eos > 1 || !(rp->kappa_P >= 0) || !(rp->kappa_R >= 0) ||
-      (rp->eos == 1 && !(rp->alpha_cv > 0)))
+      (rp->eos == 1 && !(rp->alpha_cv > 0)) || rp->reconstruction < 0 || rp->reconstruction > 1)
     return fail(ctx, QK_EINVAL, "invalid radiation parameters");
   return QK_OK;
 }
@@ -276,7 +277,8 @@ void launch_flatten(const HostBox& hb, const S* U, R* chi, double gamma, hipStre
 
 template <class S, class R, int STAGE>
 void launch_stage(const HostBox& hb, const S* Uin, const S* Un, S* Uout, const R* chi, double gamma,
-                  const double* dt_ptr, double dt_val, unsigned long long* smax, uint32_t* err, hipStream_t s) {
+                  const double* dt_ptr, double dt_val, unsigned long long* smax, uint32_t* err, int recon,
+                  hipStream_t s) {
   const DevBox& d = hb.d;
   Launch L = plan(d.n0, d.n1, d.n2, HTX, HTY, 2048);
   StageArgs<S, R> a;
@@ -294,6 +296,7 @@ void launch_stage(const HostBox& hb, const S* Uin, const S* Un, S* Uout, const R
   a.gy = L.gy;
   a.smax = smax;
   a.err = err;
+  a.recon = recon;
   hipLaunchKernelGGL((stage_kernel<S, R, HTX, HTY, STAGE>), dim3(L.gx * L.gy * L.gz), dim3(HTX * HTY), 0, s, a);
 }
 
@@ -335,7 +338,7 @@ qk_status hydro_step_t(qk_ctx* ctx, const HostBox& hb, S* U, const qk_hydro_para
   launch_flatten<S, R>(hb, U, chi, hp->gamma, s);
   T.end(QK_K_FLATTEN, s);
   T.begin(QK_K_HYDRO_STAGE, s);
-  launch_stage<S, R, 1>(hb, U, U, U1, chi, hp->gamma, dtp, dtv, nullptr, &ctx->sc->err, s);
+  launch_stage<S, R, 1>(hb, U, U, U1, chi, hp->gamma, dtp, dtv, nullptr, &ctx->sc->err, hp->reconstruction, s);
   T.end(QK_K_HYDRO_STAGE, s);
   T.begin(QK_K_GHOST, s);
   launch_ghosts<S>(hb, U1, 5, s);
@@ -345,7 +348,7 @@ qk_status hydro_step_t(qk_ctx* ctx, const HostBox& hb, S* U, const qk_hydro_para
   T.end(QK_K_FLATTEN, s);
   T.begin(QK_K_HYDRO_STAGE, s);
   launch_stage<S, R, 2>(hb, U1, U, U, chi, hp->gamma, dtp, dtv, dt_next ? &ctx->sc->smax_b : nullptr,
-                        &ctx->sc->err, s);
+                        &ctx->sc->err, hp->reconstruction, s);
   T.end(QK_K_HYDRO_STAGE, s);
   T.begin(QK_K_GHOST, s);
   launch_ghosts<S>(hb, U, 5, s);

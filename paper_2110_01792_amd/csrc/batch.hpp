@@ -23,6 +23,7 @@ struct BatchBox {
   S* Ur1;    // radiation stage buffer (library scratch) or NULL
   double gamma;
   int zc_stage, zc_flat;
+  int recon;  // hydro reconstruction of this box (0 PPM, 1 PLM)
 };
 
 struct WorkItem {
@@ -90,6 +91,7 @@ __global__ __launch_bounds__(TX* TY) void batch_stage_kernel(const BatchBox<S, R
     a.gx = a.gy = 1;
     a.smax = nullptr;
     a.err = err;
+    a.recon = bb.recon;
     stage_tile<S, R, TX, TY, STAGE>(a, w.bx, w.by, w.bz, sm, bad);
     __syncthreads();
   }

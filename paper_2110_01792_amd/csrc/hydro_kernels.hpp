@@ -32,6 +32,7 @@ struct StageArgs {
   double dt_val;
   int zc;                // planes per block
   int gx, gy;            // tiles along x and y
+  int recon;             // 0 PPM, 1 PLM
   unsigned long long* smax;  // stage 2: max(|v| + c_s) of the new state (ordered bits), or NULL
   uint32_t* err;
 };
@@ -218,8 +219,8 @@ __global__ __launch_bounds__(TX* TY) void flatten_kernel(FlatArgs<S, R> a, int g
 // cell reads Un only at itself).
 // ---------------------------------------------------------------------------
 template <class R>
-__device__ __forceinline__ void ppm_flat(const R* q, R chi, R& l, R& r) {
-  ppm<R>(q[0], q[1], q[2], q[3], q[4], l, r);
+__device__ __forceinline__ void ppm_flat(const R* q, R chi, int recon, R& l, R& r) {
+  recon5<R>(q[0], q[1], q[2], q[3], q[4], recon, l, r);
   l = chi * l + (R(1) - chi) * q[2];
   r = chi * r + (R(1) - chi) * q[2];
 }
@@ -288,7 +289,7 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       R q[5] = {w[v][0], w[v][1], w[v][2], w[v][3], w[v][4]};
-      ppm_flat<R>(q, ch, l[v], r[v]);
+      ppm_flat<R>(q, ch, a.recon, l[v], r[v]);
     }
     L[0] = l[0]; L[1] = l[3]; L[2] = l[1]; L[3] = l[2]; L[4] = l[4];
     Rr[0] = r[0]; Rr[1] = r[3]; Rr[2] = r[1]; Rr[3] = r[2]; Rr[4] = r[4];
@@ -362,7 +363,7 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
       for (int v = 0; v < 5; ++v) {
         const R* row = &Wp[v][yy + 3][xx + 1];
         R q[5] = {row[0], row[1], row[2], row[3], row[4]};
-        ppm_flat<R>(q, ch, recL[v][it], recR[v][it]);
+        ppm_flat<R>(q, ch, a.recon, recL[v][it], recR[v][it]);
       }
     }
     __syncthreads();
@@ -395,7 +396,7 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
       for (int v = 0; v < 5; ++v) {
         R q[5] = {Wp[v][yy + 1][xx + 3], Wp[v][yy + 2][xx + 3], Wp[v][yy + 3][xx + 3], Wp[v][yy + 4][xx + 3],
                   Wp[v][yy + 5][xx + 3]};
-        ppm_flat<R>(q, ch, recL[v][it], recR[v][it]);
+        ppm_flat<R>(q, ch, a.recon, recL[v][it], recR[v][it]);
       }
     }
     __syncthreads();

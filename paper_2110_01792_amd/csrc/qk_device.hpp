@@ -57,6 +57,26 @@ __device__ __forceinline__ void ppm(R qm2, R qm1, R q0, R qp1, R qp2, R& aL, R& 
   aR = ext ? q0 + R(0.5) * s : fr2;
 }
 
+// PLM with the monotonized-central limiter (Section 2.2.1 alternative).
+template <class R>
+__device__ __forceinline__ void plm(R qm1, R q0, R qp1, R& aL, R& aR) {
+  const R dl = q0 - qm1, dr = qp1 - q0, dc = qp1 - qm1;
+  R s = rmin(rmin(R(2) * fabs(dr), R(2) * fabs(dl)), R(0.5) * fabs(dc));
+  s = (dc < R(0)) ? -s : s;
+  s = (dr * dl > R(0)) ? s : R(0);
+  aL = q0 - R(0.5) * s;
+  aR = q0 + R(0.5) * s;
+}
+
+// Reconstruction selected at run time (uniform across the launch).
+template <class R>
+__device__ __forceinline__ void recon5(R qm2, R qm1, R q0, R qp1, R qp2, int recon, R& aL, R& aR) {
+  if (recon == 1)
+    plm<R>(qm1, q0, qp1, aL, aR);
+  else
+    ppm<R>(qm2, qm1, q0, qp1, qp2, aL, aR);
+}
+
 // ---------------------------------------------------------------------------
 // HLLC flux with PVRS wave speeds (Section 2.2.1; Toro ch. 10).  States are
 // primitive (rho, u_normal, u_t1, u_t2, P).  Output flux in the same rotated

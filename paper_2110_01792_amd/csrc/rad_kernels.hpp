@@ -17,7 +17,7 @@ namespace qk {
 
 struct RadParamsDev {
   double c, chat, a_r, kappa_P, kappa_R, gamma, alpha_cv, newton_tol;
-  int newton_max_iter, closure, tau_correction, eos;
+  int newton_max_iter, closure, tau_correction, eos, recon;
 };
 
 template <class S, class R>
@@ -235,7 +235,7 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
   };
   auto recon_z = [&](R* L, R* Rr) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) ppm<R>(w[v][0], w[v][1], w[v][2], w[v][3], w[v][4], L[v], Rr[v]);
+    for (int v = 0; v < 4; ++v) recon5<R>(w[v][0], w[v][1], w[v][2], w[v][3], w[v][4], p.recon, L[v], Rr[v]);
   };
   auto rho_at = [&](int kk) { return R(a.Ug[cell(b, i, j, kk)]); };
 
@@ -317,7 +317,7 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const R* row = &Qp[v][yy + 3][xx + 1];
-        ppm<R>(row[0], row[1], row[2], row[3], row[4], recL[v][it], recR[v][it]);
+        recon5<R>(row[0], row[1], row[2], row[3], row[4], p.recon, recL[v][it], recR[v][it]);
       }
     }
     __syncthreads();
@@ -350,8 +350,8 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
       const int xx = it % tw, yy = it / tw - 1;
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        ppm<R>(Qp[v][yy + 1][xx + 3], Qp[v][yy + 2][xx + 3], Qp[v][yy + 3][xx + 3], Qp[v][yy + 4][xx + 3],
-               Qp[v][yy + 5][xx + 3], recL[v][it], recR[v][it]);
+        recon5<R>(Qp[v][yy + 1][xx + 3], Qp[v][yy + 2][xx + 3], Qp[v][yy + 3][xx + 3], Qp[v][yy + 4][xx + 3],
+                  Qp[v][yy + 5][xx + 3], p.recon, recL[v][it], recR[v][it]);
     }
     __syncthreads();
     for (int it = t; it < tw * (th + 1); it += NT) {

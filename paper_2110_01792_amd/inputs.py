@@ -162,7 +162,7 @@ def sedov(n=256, gamma=5.0 / 3.0, ng=4):
 def rad_params(chat, gamma=5.0 / 3.0, **kw):
     p = {"c": 1000.0, "chat": float(chat), "a_r": 1.0, "kappa_P": 1.0, "kappa_R": 1.0, "gamma": gamma,
          "alpha_cv": 4.0, "cfl": 0.3, "newton_tol": 1e-12, "newton_max_iter": 400, "nsub_max": 10,
-         "closure": 0, "tau_correction": 1, "eos": 0}
+         "closure": 0, "tau_correction": 1, "eos": 0, "recon": 0}
     p.update(kw)
     return p
 

@@ -20,20 +20,20 @@ def ctx():
     c.close()
 
 
-def gpu_steps(ctx, b, U, gamma, cfl, nsteps, dt=0.0):
+def gpu_steps(ctx, b, U, gamma, cfl, nsteps, dt=0.0, recon=0):
     Ud = dev(U)
     ctx.fill_ghosts(b, Ud)
-    hp = qb.hydro_params(gamma, cfl)
+    hp = qb.hydro_params(gamma, cfl, recon)
     for _ in range(nsteps):
         ctx.hydro_step(b, Ud, hp, dt=dt)
     assert ctx.sync_status() == qb.QK_OK
     return host(Ud)
 
 
-def oracle_steps(b, U, gamma, cfl, nsteps, dt=0.0):
+def oracle_steps(b, U, gamma, cfl, nsteps, dt=0.0, recon=0):
     U = U.copy()
     for _ in range(nsteps):
-        oracle.hydro_step(b, U, gamma, cfl, dt)
+        oracle.hydro_step(b, U, gamma, cfl, dt, recon=recon)
     return U
 
 
@@ -60,6 +60,21 @@ def test_shock_ragged_tiles(ctx, n):
     g = b.ng
     U[:, g:g + n[2], g:g + n[1], g:g + n[0]] = U0[:, g:g + n[2], g:g + n[1], g:g + n[0]]
     check(gpu_steps(ctx, b, U, p["gamma"], p["cfl"], 2), oracle_steps(b, U, p["gamma"], p["cfl"], 2), b)
+
+
+@pytest.mark.parametrize("n", [32, (40, 35, 27)])
+def test_plm_reconstruction(ctx, n):
+    """PLM option (Section 2.2.1): smooth periodic and ragged shock boxes."""
+    if n == 32:
+        b, U, p = inputs.hydro_smooth(n=32)
+    else:
+        b0, U0, p = inputs.hydro_shock(n=max(n))
+        b = inputs.make_box(n, bc=inputs.OUTFLOW)
+        U = np.zeros((5,) + b.shape)
+        g = b.ng
+        U[:, g:g + n[2], g:g + n[1], g:g + n[0]] = U0[:, g:g + n[2], g:g + n[1], g:g + n[0]]
+    check(gpu_steps(ctx, b, U, p["gamma"], p["cfl"], 3, recon=1),
+          oracle_steps(b, U, p["gamma"], p["cfl"], 3, recon=1), b)
 
 
 def test_shock_256_full_size(ctx):

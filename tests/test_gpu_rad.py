@@ -67,6 +67,17 @@ def test_rhd_small_and_ragged(ctx, n):
     check_pair((gg, gr), (og, orr), b, f"n={n}")
 
 
+def test_rhd_plm(ctx):
+    """PLM for hydro and radiation (the reconstruction of the paper's RHD
+    performance runs)."""
+    b, Ug, Ur, p = inputs.rhd_lognormal(n=32, seed=17)
+    q = dict(p, recon=1)
+    gg, gr, st = gpu_rhd(ctx, b, Ug, Ur, q, 2)
+    og, orr, _ = oracle_rhd(b, Ug, Ur, q, 2)
+    assert st == qb.QK_OK
+    check_pair((gg, gr), (og, orr), b, "plm")
+
+
 def test_rhd_128(ctx):
     """The RHD workload at 128^3, one step, compared everywhere."""
     b, Ug, Ur, p = inputs.rhd_lognormal(n=128)

@@ -190,3 +190,20 @@ def test_hll_diffusion_limit_speed():
     f = oracle.hll_rad(EL, [0, 0, 0], ER, [0, 0, 0], 1, p)
     S = ch / np.sqrt(3.0)
     assert np.allclose(f, [-0.5 * S * (ER - EL), 0.0, c * ch * (EL + ER) / 6.0, 0.0], rtol=1e-14)
+
+
+# ------------------------------------------------------------------ PLM
+def test_plm_mc_slope():
+    """PLM with the monotonized-central limiter (van Leer 1977): exact on lines,
+    zero slope at an extremum, slope min(2|dr|, 2|dl|, |dc|/2) otherwise."""
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        a, s = rng.normal(), rng.normal()
+        aL, aR = oracle.plm_cell([a - s, a, a + s])
+        assert abs(aL - (a - 0.5 * s)) < 1e-14 * (1 + abs(a) + abs(s))
+        assert abs(aR - (a + 0.5 * s)) < 1e-14 * (1 + abs(a) + abs(s))
+    assert oracle.plm_cell([0.0, 1.0, 0.5]) == (1.0, 1.0)
+    aL, aR = oracle.plm_cell([0.0, 1.0, 1.1])  # dl = 1, dr = 0.1: slope 2 dr = 0.2
+    assert abs(aL - 0.9) < 1e-15 and abs(aR - 1.1) < 1e-15
+    aL, aR = oracle.plm_cell([0.0, 0.45, 1.0])  # slope |dc|/2 = 0.5
+    assert abs(aL - 0.2) < 1e-15 and abs(aR - 0.7) < 1e-15

@@ -68,6 +68,34 @@ def test_sound_wave_second_order_and_magnitude():
     assert -2.3 < slope < -1.7, (errs, slope)
 
 
+def test_sound_wave_plm_second_order_and_less_accurate_than_ppm():
+    """PLM (MC limiter) option of Section 2.2.1: still second order on the sound
+    wave, with a larger error than PPM at the same resolution."""
+    gd = gold("sound_wave.json")
+    g = gd["gamma"]
+
+    def err(N, recon):
+        b = box1d(N)
+        x = (np.arange(N) + 0.5) / N
+        U0 = np.array([1.0, 0.0, 0.0, 0.0, (1.0 / g) / (g - 1.0)])[:, None] * np.ones(N)
+        U0 = U0 + gd["amplitude"] * np.array(gd["eigenvector"])[:, None] * np.sin(2 * np.pi * x)[None, :]
+        U = np.zeros((5,) + b.shape)
+        set_line(b, U, U0)
+        t, n = 0.0, 0
+        while t < 1.0 * (1 - 1e-14):
+            oracle.fill_ghosts(b, U)
+            dt = gd["cfl"] * (1.0 / N) / oracle.hydro_max_signal(b, U, g)
+            dt = min(dt, 1.0 - t)
+            oracle.hydro_step(b, U, g, gd["cfl"], dt, recon=recon)
+            t += dt
+        return float(np.sqrt(np.sum(np.abs(line(b, U) - U0).mean(axis=1) ** 2)))
+
+    e32, e128 = err(32, 1), err(128, 1)
+    slope = np.log(e128 / e32) / np.log(4.0)
+    assert -2.4 < slope < -1.6, (e32, e128, slope)
+    assert e128 > err(128, 0)
+
+
 # -------------------------------------------------------- P3 shock capturing
 def run_tube(WL, WR, g, N, L, x0, cfl, t_end):
     b = box1d(N, L=L, bc=OUTFLOW)
