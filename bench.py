@@ -26,7 +26,14 @@ import numpy as np  # noqa: E402
 
 METRIC = "cell updates/s (hydro, RHD) 256^3 on 1 MI355X; % of HBM roofline; FP32 err"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64 (FMA counted as two)
 HYDRO_BYTES_PER_CELL_STEP = 200.0  # stage 1: read 40 + write 40; stage 2: read 80 + write 40 (FP64)
+# FP64 operations (add, sub, mul, div, sqrt each one) of one cell in one fused
+# RK stage, each interface and cell counted once: PPM + flattening blend
+# 45 x 15 (5 variables, 3 axes), HLLC 106 x 3 faces, conserved -> primitive
+# 13, flux differences and RK update 57.5 (mean of the stages), CFL signal of
+# stage 2 11 (mean).
+HYDRO_FLOPS_PER_CELL_STAGE = 45 * 15 + 106 * 3 + 13 + 57.5 + 11
 
 
 def log(*a):
@@ -81,6 +88,7 @@ def bench_hydro(ctx, qb, inputs, torch, steps, warmup, dtype):
     # algorithmic bytes per stage launch: average of the two stages
     bytes_per_launch = ncell * HYDRO_BYTES_PER_CELL_STEP * scale / 2.0
     out["stage_achieved_GBs"] = bytes_per_launch / (out["stage_ms_avg"] * 1e-3) / 1e9
+    out["stage_achieved_TFLOPs"] = ncell * HYDRO_FLOPS_PER_CELL_STAGE / (out["stage_ms_avg"] * 1e-3) / 1e12
     del Ud
     torch.cuda.empty_cache()
     return out, b, p
@@ -276,15 +284,21 @@ def main():
     b32 = bench_batch(ctx, qb, inputs, torch, max(2, args.steps // 4), torch.float32)
     log("batch:", b64, b32)
 
+    # The fused stage does ~1075 FP64 operations per ~100 HBM bytes (10.8
+    # flop/B, above the FP64 ridge 78.6 TF/s / 8 TB/s = 9.8 flop/B): it is
+    # bound by FP64 vector arithmetic; its HBM rate is reported beside it.
     roof = {
-        "bound": "hbm",
-        "achieved": round(h64["stage_achieved_GBs"], 1),
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(h64["stage_achieved_GBs"] / HBM_PEAK_GBS, 4),
+        "bound": "alu",
+        "achieved": round(h64["stage_achieved_TFLOPs"], 3),
+        "peak": FP64_PEAK_TFLOPS,
+        "unit": "TFLOP/s",
+        "frac": round(h64["stage_achieved_TFLOPs"] / FP64_PEAK_TFLOPS, 4),
         "traffic": None,
-        "kernel": "stage_kernel<double,double,16,16,1|2> (fused hydro RK stage)",
+        "kernel": "stage_kernel<double,double,1|2> (fused hydro RK stage, 16x14 tiles)",
+        "flops_per_cell_launch": HYDRO_FLOPS_PER_CELL_STAGE,
         "bytes_per_cell_launch": HYDRO_BYTES_PER_CELL_STEP / 2,
+        "hbm_achieved_GBs": round(h64["stage_achieved_GBs"], 1),
+        "hbm_frac": round(h64["stage_achieved_GBs"] / HBM_PEAK_GBS, 4),
     }
     line = {
         "metric": METRIC,

@@ -240,7 +240,7 @@ void launch_ghost_copy(const HostBox& hb, S* dst, const S* src, int nvar, hipStr
   hipLaunchKernelGGL(ghost_copy_kernel<S>, dim3(grid_for(total, 256, 8192)), dim3(256), 0, s, dst, src, d, nvar);
 }
 
-// Tile shape and z-chunk of the hydro stage for one box.
+// Tile shape of the flattening pass for one box (the stage uses STX x STY).
 constexpr int HTX = 16, HTY = 16;
 
 struct Launch {
@@ -280,7 +280,7 @@ void launch_stage(const HostBox& hb, const S* Uin, const S* Un, S* Uout, const R
                   const double* dt_ptr, double dt_val, unsigned long long* smax, uint32_t* err, int recon,
                   hipStream_t s) {
   const DevBox& d = hb.d;
-  Launch L = plan(d.n0, d.n1, d.n2, HTX, HTY, 2048);
+  Launch L = plan(d.n0, d.n1, d.n2, STX, STY, 2048);
   StageArgs<S, R> a;
   a.Uin = Uin;
   a.Ugh = nullptr;
@@ -297,7 +297,7 @@ void launch_stage(const HostBox& hb, const S* Uin, const S* Un, S* Uout, const R
   a.smax = smax;
   a.err = err;
   a.recon = recon;
-  hipLaunchKernelGGL((stage_kernel<S, R, HTX, HTY, STAGE>), dim3(L.gx * L.gy * L.gz), dim3(HTX * HTY), 0, s, a);
+  hipLaunchKernelGGL((stage_kernel<S, R, STAGE>), dim3(L.gx * L.gy * L.gz), dim3(SNT), 0, s, a);
 }
 
 template <class S>

@@ -69,7 +69,7 @@ template <class S, class R, int TX, int TY, int STAGE>
 __global__ __launch_bounds__(TX* TY) void batch_stage_kernel(const BatchBox<S, R>* __restrict__ boxes,
                                                              const WorkItem* __restrict__ items, int nitems,
                                                              int* counter, const double* dt_ptr, uint32_t* err) {
-  __shared__ HydroSmem<R, TX, TY> sm;
+  __shared__ HydroSmem<R, TX, TY, false> sm;
   __shared__ int slot;
   bool bad = false;
   for (;;) {
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(TX* TY) void batch_stage_kernel(const BatchBox<S, R
     a.smax = nullptr;
     a.err = err;
     a.recon = bb.recon;
-    stage_tile<S, R, TX, TY, STAGE>(a, w.bx, w.by, w.bz, sm, bad);
+    stage_tile<S, R, TX, TY, TX * TY, false, STAGE>(a, w.bx, w.by, w.bz, sm, bad);
     __syncthreads();
   }
   if (bad) atomicOr(err, ERR_NEG);
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(TX* TY, 2) void batch_rad_kernel(const BatchBox<S, 
                                                               uint32_t* iter_max) {
   const int N = *nsub_ptr;
   if (sub >= N) return;
-  __shared__ RadSmem<R, TX, TY> sm;
+  __shared__ RadSmem<R, TX, TY, false> sm;
   __shared__ int slot;
   bool bad = false, nfail = false;
   uint32_t itmax = 0;
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(TX* TY, 2) void batch_rad_kernel(const BatchBox<S, 
     a.gx = a.gy = 1;
     a.err = err;
     a.iter_max = iter_max;
-    itmax = max(itmax, rad_tile<S, R, TX, TY, STAGE>(a, w.bx, w.by, w.bz, N, sm, bad, nfail));
+    itmax = max(itmax, rad_tile<S, R, TX, TY, TX * TY, false, STAGE>(a, w.bx, w.by, w.bz, N, sm, bad, nfail));
     __syncthreads();
   }
   if (bad) atomicOr(err, ERR_NEG);

@@ -106,11 +106,37 @@ struct FlatSmem {
   R cty[TY + 2][TX];
 };
 
-// One tile of columns (tile indices over the grown range [-1, n]).
+// One cell of a plane's halo ring that a thread loads for every plane of its
+// tile: its state array, its offset in plane 0 (add k * pz), its flat index in
+// the LDS plane and its kind (0 none, 1 primitive state, 2 flattening value).
+template <class S>
+struct HaloCell {
+  const S* src;
+  int64_t off;
+  int lds, kind;
+};
+
+// Prefetch of one halo cell at plane offset pl: NV state variables (kind 1)
+// or one value of the auxiliary per-cell array (kind 2) into q (as double).
+template <int NV, class S, class T>
+__device__ __forceinline__ void load_halo(const HaloCell<S>& h, const S* src, const T* aux, int64_t pl, int64_t vs,
+                                          double* q) {
+  if (h.kind == 1) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) q[v] = double(src[h.off + pl + v * vs]);
+  } else if (h.kind == 2) {
+    q[0] = double(aux[h.off + pl]);
+  }
+}
+
+// One tile of columns (tile indices over the grown range [-1, n]).  The
+// tile's own cells come from each thread's z window; the 3-cell halo ring of
+// each plane is prefetched one plane ahead into registers.
 template <class S, class R, int TX, int TY>
 __device__ __forceinline__ void flatten_tile(const FlatArgs<S, R>& a, int tbx, int tby, int tbz,
                                              FlatSmem<R, TX, TY>& sm) {
   constexpr int NT = TX * TY;
+  constexpr int NHX = 6 * TY, NHY = 6 * TX, NH = NHX + NHY, HPT = (NH + NT - 1) / NT;
   const DevBox& b = a.b;
   const int t = threadIdx.x, tx = t % TX, ty = t / TX;
   const int xs = -1 + tbx * TX, ys = -1 + tby * TY;
@@ -119,27 +145,68 @@ __device__ __forceinline__ void flatten_tile(const FlatArgs<S, R>& a, int tbx, i
   const int ze = min(zs + a.zc, b.n2 + 1);
   const bool act = tx < tw && ty < th;
   const int i = xs + tx, j = ys + ty;
-  const int64_t vs = b.vs;
+  const int64_t vs = b.vs, pz = b.pz;
   const double gm1 = a.gm1;
   bool bad = false;
 
-  R P[7], uz[7];  // own column, planes k-3 .. k+3
-  R cz[3];        // chi_tilde_z at k-1, k, k+1
-  auto col = [&](int kk, R& p, R& w) {
-    double q[5];
-    load_cons(src_at(a.U, a.Ugh, b, i, j, kk), vs, cell(b, i, j, kk), q);
+  HaloCell<S> hc[HPT];
+#pragma unroll
+  for (int m = 0; m < HPT; ++m) {
+    const int it = t + m * NT;
+    int xx = 0, yy = 0, kind = 0;
+    if (it < NHX) {
+      const int c = it % 6;
+      yy = it / 6;
+      xx = c < 3 ? c - 3 : tw + c - 3;
+      kind = yy < th ? 1 : 0;
+    } else if (it < NH) {
+      const int r = it - NHX, c = r / TX;
+      xx = r % TX;
+      yy = c < 3 ? c - 3 : th + c - 3;
+      kind = xx < tw ? 1 : 0;
+    }
+    hc[m].kind = kind;
+    hc[m].src = src_at(a.U, a.Ugh, b, xs + xx, ys + yy, 0);
+    hc[m].off = cell(b, xs + xx, ys + yy, 0);
+    hc[m].lds = (yy + 3) * (TX + 6) + (xx + 3);
+  }
+  // planes -1 and n of the grown range lie outside the interior in z
+  auto hsrc = [&](const HaloCell<S>& h, int kk) {
+    return (a.Ugh && (unsigned)kk >= (unsigned)b.n2) ? a.Ugh : h.src;
+  };
+
+  R P[7], uz[7];    // own column, planes k-3 .. k+3
+  R uxq[4], uyq[4];  // own column, planes k .. k+3
+  R cz[3];           // chi_tilde_z at k-1, k, k+1
+  double cq[5];      // conserved state of plane k+3 (prefetched)
+  double hq[HPT][5];  // halo ring of plane k (prefetched)
+  auto prim = [&](const double* q, R& p, R& ux, R& uy, R& w) {
     R W[5];
     cons_to_prim<R>(q[0], q[1], q[2], q[3], q[4], gm1, W, bad);
-    p = W[4];
+    ux = W[1];
+    uy = W[2];
     w = W[3];
+    p = W[4];
   };
   if (act) {
 #pragma unroll
-    for (int s = 0; s < 6; ++s) col(zs - 3 + s, P[s + 1], uz[s + 1]);
-    // window holds planes zs-3..zs+2 in slots 1..6; chi_tilde_z(zs-1), (zs)
+    for (int s = 0; s < 6; ++s) {
+      const int kk = zs - 3 + s;
+      double q[5];
+      load_cons(src_at(a.U, a.Ugh, b, i, j, kk), vs, cell(b, i, j, kk), q);
+      R ux, uy;
+      prim(q, P[s + 1], ux, uy, uz[s + 1]);
+      if (s >= 3) {
+        uxq[s - 2] = ux;
+        uyq[s - 2] = uy;
+      }
+    }
     cz[1] = chi_tilde<R>(P[1], P[2], P[4], P[5], uz[2], uz[4]);
     cz[2] = chi_tilde<R>(P[2], P[3], P[5], P[6], uz[3], uz[5]);
+    load_cons(src_at(a.U, a.Ugh, b, i, j, zs + 3), vs, cell(b, i, j, zs + 3), cq);
   }
+#pragma unroll
+  for (int m = 0; m < HPT; ++m) load_halo<5>(hc[m], hsrc(hc[m], zs), (const R*)nullptr, (int64_t)zs * pz, vs, hq[m]);
 
   for (int k = zs; k < ze; ++k) {
     if (act) {
@@ -148,48 +215,52 @@ __device__ __forceinline__ void flatten_tile(const FlatArgs<S, R>& a, int tbx, i
         P[s] = P[s + 1];
         uz[s] = uz[s + 1];
       }
-      col(k + 3, P[6], uz[6]);
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        uxq[s] = uxq[s + 1];
+        uyq[s] = uyq[s + 1];
+      }
+      prim(cq, P[6], uxq[3], uyq[3], uz[6]);
       cz[0] = cz[1];
       cz[1] = cz[2];
       cz[2] = chi_tilde<R>(P[2], P[3], P[5], P[6], uz[3], uz[5]);  // at k+1
+      sm.Pp[ty + 3][tx + 3] = P[3];
+      sm.uxp[ty + 3][tx + 3] = uxq[0];
+      sm.uyp[ty + 3][tx + 3] = uyq[0];
     }
-    // in-plane primitives over the cross-shaped region |dx| <= 3 or |dy| <= 3
-    const int ncore = tw * th, nxh = 6 * th, nyh = 6 * tw;
-    for (int it = t; it < ncore + nxh + nyh; it += NT) {
-      int xx, yy;
-      if (it < ncore) {
-        xx = it % tw;
-        yy = it / tw;
-      } else if (it < ncore + nxh) {
-        const int r = it - ncore, c = r % 6;
-        yy = r / 6;
-        xx = c < 3 ? c - 3 : tw + c - 3;
-      } else {
-        const int r = it - ncore - nxh, c = r / tw;
-        xx = r % tw;
-        yy = c < 3 ? c - 3 : th + c - 3;
+#pragma unroll
+    for (int m = 0; m < HPT; ++m) {
+      if (hc[m].kind == 1) {
+        bool dummy = false;
+        R W[5];
+        cons_to_prim<R>(hq[m][0], hq[m][1], hq[m][2], hq[m][3], hq[m][4], gm1, W, dummy);
+        (&sm.Pp[0][0])[hc[m].lds] = W[4];
+        (&sm.uxp[0][0])[hc[m].lds] = W[1];
+        (&sm.uyp[0][0])[hc[m].lds] = W[2];
       }
-      double q[5];
-      const int gi = xs + xx, gj = ys + yy;
-      load_cons(src_at(a.U, a.Ugh, b, gi, gj, k), vs, cell(b, gi, gj, k), q);
-      R W[5];
-      cons_to_prim<R>(q[0], q[1], q[2], q[3], q[4], gm1, W, bad);
-      sm.Pp[yy + 3][xx + 3] = W[4];
-      sm.uxp[yy + 3][xx + 3] = W[1];
-      sm.uyp[yy + 3][xx + 3] = W[2];
+    }
+    if (k + 1 < ze) {
+      if (act) load_cons(src_at(a.U, a.Ugh, b, i, j, k + 4), vs, cell(b, i, j, k + 4), cq);
+#pragma unroll
+      for (int m = 0; m < HPT; ++m)
+        load_halo<5>(hc[m], hsrc(hc[m], k + 1), (const R*)nullptr, (int64_t)(k + 1) * pz, vs, hq[m]);
     }
     __syncthreads();
-    for (int it = t; it < (tw + 2) * th; it += NT) {
-      const int xx = it % (tw + 2) - 1, yy = it / (tw + 2);
-      const int X = xx + 3, Y = yy + 3;
-      sm.ctx[yy][xx + 1] = chi_tilde<R>(sm.Pp[Y][X - 2], sm.Pp[Y][X - 1], sm.Pp[Y][X + 1], sm.Pp[Y][X + 2],
-                                        sm.uxp[Y][X - 1], sm.uxp[Y][X + 1]);
+    for (int it = t; it < (TX + 2) * TY; it += NT) {
+      const int xx = it % (TX + 2) - 1, yy = it / (TX + 2);
+      if (xx <= tw && yy < th) {
+        const int X = xx + 3, Y = yy + 3;
+        sm.ctx[yy][xx + 1] = chi_tilde<R>(sm.Pp[Y][X - 2], sm.Pp[Y][X - 1], sm.Pp[Y][X + 1], sm.Pp[Y][X + 2],
+                                          sm.uxp[Y][X - 1], sm.uxp[Y][X + 1]);
+      }
     }
-    for (int it = t; it < tw * (th + 2); it += NT) {
-      const int xx = it % tw, yy = it / tw - 1;
-      const int X = xx + 3, Y = yy + 3;
-      sm.cty[yy + 1][xx] = chi_tilde<R>(sm.Pp[Y - 2][X], sm.Pp[Y - 1][X], sm.Pp[Y + 1][X], sm.Pp[Y + 2][X],
-                                        sm.uyp[Y - 1][X], sm.uyp[Y + 1][X]);
+    for (int it = t; it < TX * (TY + 2); it += NT) {
+      const int xx = it % TX, yy = it / TX - 1;
+      if (xx < tw && yy <= th) {
+        const int X = xx + 3, Y = yy + 3;
+        sm.cty[yy + 1][xx] = chi_tilde<R>(sm.Pp[Y - 2][X], sm.Pp[Y - 1][X], sm.Pp[Y + 1][X], sm.Pp[Y + 2][X],
+                                          sm.uyp[Y - 1][X], sm.uyp[Y + 1][X]);
+      }
     }
     __syncthreads();
     if (act) {
@@ -225,28 +296,43 @@ __device__ __forceinline__ void ppm_flat(const R* q, R chi, int recon, R& l, R& 
   r = chi * r + (R(1) - chi) * q[2];
 }
 
-template <class R, int TX, int TY>
+// LDS of one stage tile.  SPLIT: x and y face states and fluxes have buffers
+// of their own, so both sweeps reconstruct in one phase and solve their faces
+// in the next (three barriers per plane).  Otherwise the y sweep reuses the
+// x sweep's buffers after it (five barriers, less LDS).
+template <class R, int TX, int TY, bool SPLIT>
 struct HydroSmem {
-  static constexpr int NREC = ((TX + 2) * TY > TX * (TY + 2)) ? (TX + 2) * TY : TX * (TY + 2);
-  static constexpr int NFL = ((TX + 1) * TY > TX * (TY + 1)) ? (TX + 1) * TY : TX * (TY + 1);
+  static constexpr int NXR = (TX + 2) * TY, NYR = TX * (TY + 2);
+  static constexpr int NXF = (TX + 1) * TY, NYF = TX * (TY + 1);
+  static constexpr int XS = SPLIT ? NXR : (NXR > NYR ? NXR : NYR);  // x (shared) state buffer length
+  static constexpr int XFS = SPLIT ? NXF : (NXF > NYF ? NXF : NYF);
+  static constexpr int YS = SPLIT ? NYR : XS, YFS = SPLIT ? NYF : XFS;
   R Wp[5][TY + 6][TX + 6];
   R chiP[TY + 2][TX + 2];
-  R recL[5][NREC];
-  R recR[5][NREC];
-  R fl[5][NFL];
+  R xL[5][XS], xR[5][XS];
+  R xF[5][XFS];
+  R yL[5][SPLIT ? NYR : 1], yR[5][SPLIT ? NYR : 1];
+  R yF[5][SPLIT ? NYF : 1];
 };
 
 // One tile of columns of one box: returns the thread's max(|v| + c_s) of the
 // new state (stage 2 with a.smax set), sets `bad` on a non-positive state.
-template <class S, class R, int TX, int TY, int STAGE>
+// NT threads (NT >= TX*TY); thread t owns column (t % TX, t / TX).
+template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE>
 __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, int tby, int tbz,
-                                             HydroSmem<R, TX, TY>& sm, bool& bad_out) {
-  constexpr int NT = TX * TY;
-  auto& Wp = sm.Wp;
-  auto& chiP = sm.chiP;
-  auto& recL = sm.recL;
-  auto& recR = sm.recR;
-  auto& fl = sm.fl;
+                                             HydroSmem<R, TX, TY, SPLIT>& sm, bool& bad_out) {
+  using SM = HydroSmem<R, TX, TY, SPLIT>;
+  constexpr int NXR = SM::NXR, NYR = SM::NYR, NXF = SM::NXF, NYF = SM::NYF;
+  constexpr int XS = SM::XS, YS = SM::YS, XFS = SM::XFS, YFS = SM::YFS;
+  constexpr int NHX = 6 * TY, NHY = 6 * TX, NCX = 2 * TY, NCY = 2 * TX;
+  constexpr int NH = NHX + NHY + NCX + NCY, HPT = (NH + NT - 1) / NT;
+  static_assert(NT >= TX * TY, "one thread per column");
+  R* const xL = &sm.xL[0][0];
+  R* const xR = &sm.xR[0][0];
+  R* const xF = &sm.xF[0][0];
+  R* const yL = SPLIT ? &sm.yL[0][0] : xL;
+  R* const yR = SPLIT ? &sm.yR[0][0] : xR;
+  R* const yF = SPLIT ? &sm.yF[0][0] : xF;
 
   const DevBox& b = a.b;
   const int t = threadIdx.x, tx = t % TX, ty = t / TX;
@@ -256,7 +342,7 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
   const int z1 = min(z0 + a.zc, b.n2);
   const bool act = tx < tw && ty < th;
   const int i = x0 + tx, j = y0 + ty;
-  const int64_t vs = b.vs;
+  const int64_t vs = b.vs, pz = b.pz;
   const double dt = a.dt_ptr ? *a.dt_ptr : a.dt_val;
   const double gm1 = a.gamma - 1.0;
   const GasK<R> g = gas_k<R>(a.gamma);
@@ -264,16 +350,58 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
   const R* __restrict__ chi = a.chi;
   bool bad = false;
 
+  // halo ring of every plane: 3 cells of state beyond each x and y edge of
+  // the tile, 1 cell of flattening coefficients
+  HaloCell<S> hc[HPT];
+#pragma unroll
+  for (int m = 0; m < HPT; ++m) {
+    const int it = t + m * NT;
+    int xx = 0, yy = 0, kind = 0, lds = 0;
+    if (it < NHX) {
+      const int c = it % 6;
+      yy = it / 6;
+      xx = c < 3 ? c - 3 : tw + c - 3;
+      kind = yy < th ? 1 : 0;
+    } else if (it < NHX + NHY) {
+      const int r = it - NHX, c = r / TX;
+      xx = r % TX;
+      yy = c < 3 ? c - 3 : th + c - 3;
+      kind = xx < tw ? 1 : 0;
+    } else if (it < NHX + NHY + NCX) {
+      const int r = it - NHX - NHY;
+      yy = r >> 1;
+      xx = (r & 1) ? tw : -1;
+      kind = yy < th ? 2 : 0;
+    } else if (it < NH) {
+      const int r = it - NHX - NHY - NCX;
+      xx = r % TX;
+      yy = (r / TX) ? th : -1;
+      kind = xx < tw ? 2 : 0;
+    }
+    lds = kind == 2 ? (yy + 1) * (TX + 2) + (xx + 1) : (yy + 3) * (TX + 6) + (xx + 3);
+    hc[m].kind = kind;
+    hc[m].src = src_at(Uin, a.Ugh, b, x0 + xx, y0 + yy, z0);
+    hc[m].off = cell(b, x0 + xx, y0 + yy, 0);
+    hc[m].lds = lds;
+  }
+
   R w[5][5];  // own column primitives: [var][plane slot], slot s = plane m-2+s
   R aRz[5], Fz[5];
+  double cq[5];       // conserved state of own column, plane k+3 (prefetched)
+  double hq[HPT][5];  // halo ring of plane k (prefetched)
+  double uo[5], un[5];
+  R chk = R(0);       // chi of own cell, plane k
 
-  auto load_w = [&](int kk, int slot) {
-    double q[5];
-    load_cons(src_at(Uin, a.Ugh, b, i, j, kk), vs, cell(b, i, j, kk), q);
+  auto prim_w = [&](const double* q, int slot) {
     R W[5];
     cons_to_prim<R>(q[0], q[1], q[2], q[3], q[4], gm1, W, bad);
 #pragma unroll
     for (int v = 0; v < 5; ++v) w[v][slot] = W[v];
+  };
+  auto load_w = [&](int kk, int slot) {
+    double q[5];
+    load_cons(src_at(Uin, a.Ugh, b, i, j, kk), vs, cell(b, i, j, kk), q);
+    prim_w(q, slot);
   };
   auto shift_w = [&]() {
 #pragma unroll
@@ -303,128 +431,157 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
     shift_w();
     load_w(z0 + 2, 4);  // centred on z0
     R rcur[5];
-    recon_z(chi[cell(b, i, j, z0)], l, rcur);
+    chk = chi[cell(b, i, j, z0)];
+    recon_z(chk, l, rcur);
     hllc<R>(rprev, l, g, Fz);
 #pragma unroll
     for (int v = 0; v < 5; ++v) aRz[v] = rcur[v];
+    load_cons(src_at(Uin, a.Ugh, b, i, j, z0 + 3), vs, cell(b, i, j, z0 + 3), cq);
   }
+#pragma unroll
+  for (int m = 0; m < HPT; ++m) load_halo<5>(hc[m], hc[m].src, chi, (int64_t)z0 * pz, vs, hq[m]);
   bad = false;
   double smax = 0.0;
 
   for (int k = z0; k < z1; ++k) {
+    R chn = R(0);
     if (act) {
       shift_w();
-      load_w(k + 3, 4);  // window: planes k-1 .. k+3; plane k in slot 1
+      prim_w(cq, 4);  // window: planes k-1 .. k+3; plane k in slot 1
 #pragma unroll
-      for (int v = 0; v < 5; ++v) Wp[v][ty + 3][tx + 3] = w[v][1];
-      chiP[ty + 1][tx + 1] = chi[cell(b, i, j, k)];
+      for (int v = 0; v < 5; ++v) sm.Wp[v][ty + 3][tx + 3] = w[v][1];
+      sm.chiP[ty + 1][tx + 1] = chk;
     }
-    {
-      const int nxh = 6 * th, nyh = 6 * tw, nh = nxh + nyh;
-      const int ncx = 2 * th, ncy = 2 * tw;
-      for (int it = t; it < nh + ncx + ncy; it += NT) {
-        if (it < nh) {
-          int xx, yy;
-          if (it < nxh) {
-            const int c = it % 6;
-            yy = it / 6;
-            xx = c < 3 ? c - 3 : tw + c - 3;
-          } else {
-            const int r = it - nxh, c = r / tw;
-            xx = r % tw;
-            yy = c < 3 ? c - 3 : th + c - 3;
-          }
-          double q[5];
-          const int gi = x0 + xx, gj = y0 + yy;
-          load_cons(src_at(Uin, a.Ugh, b, gi, gj, k), vs, cell(b, gi, gj, k), q);
-          R W[5];
-          bool dummy = false;
-          cons_to_prim<R>(q[0], q[1], q[2], q[3], q[4], gm1, W, dummy);
 #pragma unroll
-          for (int v = 0; v < 5; ++v) Wp[v][yy + 3][xx + 3] = W[v];
-        } else if (it < nh + ncx) {
-          const int r = it - nh;
-          const int yy = r >> 1, xx = (r & 1) ? tw : -1;
-          chiP[yy + 1][xx + 1] = chi[cell(b, x0 + xx, y0 + yy, k)];
-        } else {
-          const int r = it - nh - ncx;
-          const int xx = r % tw, yy = (r / tw) ? th : -1;
-          chiP[yy + 1][xx + 1] = chi[cell(b, x0 + xx, y0 + yy, k)];
+    for (int m = 0; m < HPT; ++m) {
+      if (hc[m].kind == 1) {
+        R W[5];
+        bool dummy = false;
+        cons_to_prim<R>(hq[m][0], hq[m][1], hq[m][2], hq[m][3], hq[m][4], gm1, W, dummy);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) (&sm.Wp[v][0][0])[hc[m].lds] = W[v];
+      } else if (hc[m].kind == 2) {
+        (&sm.chiP[0][0])[hc[m].lds] = R(hq[m][0]);
+      }
+    }
+    // loads for the rest of this plane and the next one, in flight during the sweeps
+    if (act) {
+      const int64_t o = cell(b, i, j, k);
+      chn = chi[o + pz];
+      load_cons(Uin, vs, o, uo);
+      if (STAGE == 2) load_cons(a.Un, vs, o, un);
+      if (k + 1 < z1) load_cons(src_at(Uin, a.Ugh, b, i, j, k + 4), vs, o + 4 * pz, cq);
+    }
+    if (k + 1 < z1) {
+#pragma unroll
+      for (int m = 0; m < HPT; ++m) load_halo<5>(hc[m], hc[m].src, chi, (int64_t)(k + 1) * pz, vs, hq[m]);
+    }
+    __syncthreads();
+
+    auto x_recon = [&]() {
+      for (int it = t; it < NXR; it += NT) {
+        const int xx = it % (TX + 2) - 1, yy = it / (TX + 2);
+        if (xx <= tw && yy < th) {
+          const R ch = sm.chiP[yy + 1][xx + 1];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            const R* row = &sm.Wp[v][yy + 3][xx + 1];
+            R q[5] = {row[0], row[1], row[2], row[3], row[4]};
+            ppm_flat<R>(q, ch, a.recon, xL[v * XS + it], xR[v * XS + it]);
+          }
         }
       }
-    }
-    __syncthreads();
+    };
+    auto x_faces = [&]() {
+      for (int it = t; it < NXF; it += NT) {
+        const int fx = it % (TX + 1), yy = it / (TX + 1);
+        if (fx <= tw && yy < th) {
+          const int il = yy * (TX + 2) + fx, ir = il + 1;
+          R WL[5], WR[5], F[5];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            WL[v] = xR[v * XS + il];
+            WR[v] = xL[v * XS + ir];
+          }
+          hllc<R>(WL, WR, g, F);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) xF[v * XFS + it] = F[v];
+        }
+      }
+    };
+    auto y_recon = [&]() {
+      for (int it = t; it < NYR; it += NT) {
+        const int xx = it % TX, yy = it / TX - 1;
+        if (xx < tw && yy <= th) {
+          const R ch = sm.chiP[yy + 1][xx + 1];
+#pragma unroll
+          for (int v = 0; v < 5; ++v) {
+            R q[5] = {sm.Wp[v][yy + 1][xx + 3], sm.Wp[v][yy + 2][xx + 3], sm.Wp[v][yy + 3][xx + 3],
+                      sm.Wp[v][yy + 4][xx + 3], sm.Wp[v][yy + 5][xx + 3]};
+            ppm_flat<R>(q, ch, a.recon, yL[v * YS + it], yR[v * YS + it]);
+          }
+        }
+      }
+    };
+    auto y_faces = [&]() {
+      for (int it = t; it < NYF; it += NT) {
+        const int xx = it % TX, fy = it / TX;
+        if (xx < tw && fy <= th) {
+          const int il = fy * TX + xx, ir = il + TX;
+          R WL[5] = {yR[il], yR[2 * YS + il], yR[YS + il], yR[3 * YS + il], yR[4 * YS + il]};
+          R WR[5] = {yL[ir], yL[2 * YS + ir], yL[YS + ir], yL[3 * YS + ir], yL[4 * YS + ir]};
+          R F[5];
+          hllc<R>(WL, WR, g, F);
+          yF[it] = F[0];
+          yF[YFS + it] = F[2];
+          yF[2 * YFS + it] = F[1];
+          yF[3 * YFS + it] = F[3];
+          yF[4 * YFS + it] = F[4];
+        }
+      }
+    };
 
-    // ---- x sweep: reconstruct cells -1..tw of each row, then faces
-    for (int it = t; it < (tw + 2) * th; it += NT) {
-      const int xx = it % (tw + 2) - 1, yy = it / (tw + 2);
-      const R ch = chiP[yy + 1][xx + 1];
+    R dfx[5], dfy[5];
+    if constexpr (SPLIT) {
+      x_recon();
+      y_recon();
+      __syncthreads();
+      x_faces();
+      y_faces();
+      __syncthreads();
+      if (act) {
+        const int fxi = ty * (TX + 1) + tx, fyi = ty * TX + tx;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const R* row = &Wp[v][yy + 3][xx + 1];
-        R q[5] = {row[0], row[1], row[2], row[3], row[4]};
-        ppm_flat<R>(q, ch, a.recon, recL[v][it], recR[v][it]);
+        for (int v = 0; v < 5; ++v) {
+          dfx[v] = xF[v * XFS + fxi + 1] - xF[v * XFS + fxi];
+          dfy[v] = yF[v * YFS + fyi + TX] - yF[v * YFS + fyi];
+        }
+      }
+    } else {
+      x_recon();
+      __syncthreads();
+      x_faces();
+      __syncthreads();
+      if (act) {
+        const int fxi = ty * (TX + 1) + tx;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) dfx[v] = xF[v * XFS + fxi + 1] - xF[v * XFS + fxi];
+      }
+      y_recon();
+      __syncthreads();
+      y_faces();
+      __syncthreads();
+      if (act) {
+        const int fyi = ty * TX + tx;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) dfy[v] = yF[v * YFS + fyi + TX] - yF[v * YFS + fyi];
       }
     }
-    __syncthreads();
-    for (int it = t; it < (tw + 1) * th; it += NT) {
-      const int fx = it % (tw + 1), yy = it / (tw + 1);
-      const int il = yy * (tw + 2) + fx, ir = il + 1;
-      R WL[5], WR[5], F[5];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        WL[v] = recR[v][il];
-        WR[v] = recL[v][ir];
-      }
-      hllc<R>(WL, WR, g, F);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) fl[v][it] = F[v];
-    }
-    __syncthreads();
-    R dfx[5];
+
     if (act) {
-      const int f = ty * (tw + 1) + tx;
-#pragma unroll
-      for (int v = 0; v < 5; ++v) dfx[v] = fl[v][f + 1] - fl[v][f];
-    }
-
-    // ---- y sweep
-    for (int it = t; it < tw * (th + 2); it += NT) {
-      const int xx = it % tw, yy = it / tw - 1;
-      const R ch = chiP[yy + 1][xx + 1];
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        R q[5] = {Wp[v][yy + 1][xx + 3], Wp[v][yy + 2][xx + 3], Wp[v][yy + 3][xx + 3], Wp[v][yy + 4][xx + 3],
-                  Wp[v][yy + 5][xx + 3]};
-        ppm_flat<R>(q, ch, a.recon, recL[v][it], recR[v][it]);
-      }
-    }
-    __syncthreads();
-    for (int it = t; it < tw * (th + 1); it += NT) {
-      const int xx = it % tw, fy = it / tw;
-      const int il = fy * tw + xx, ir = il + tw;
-      R WL[5] = {recR[0][il], recR[2][il], recR[1][il], recR[3][il], recR[4][il]};
-      R WR[5] = {recL[0][ir], recL[2][ir], recL[1][ir], recL[3][ir], recL[4][ir]};
-      R F[5];
-      hllc<R>(WL, WR, g, F);
-      fl[0][it] = F[0];
-      fl[1][it] = F[2];
-      fl[2][it] = F[1];
-      fl[3][it] = F[3];
-      fl[4][it] = F[4];
-    }
-    __syncthreads();
-
-    if (act) {
-      R dfy[5];
-      {
-        const int f = ty * tw + tx;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) dfy[v] = fl[v][f + tw] - fl[v][f];
-      }
       // ---- z sweep: cell k+1 is centred in the window
       R aLn[5], aRn[5], Fk[5];
-      recon_z(chi[cell(b, i, j, k + 1)], aLn, aRn);
+      recon_z(chn, aLn, aRn);
       hllc<R>(aRz, aLn, g, Fk);
       // un-rotate (rho, w, u, v, E) fluxes to (rho, x, y, z, E)
       R Fn[5] = {Fk[0], Fk[2], Fk[3], Fk[1], Fk[4]};
@@ -437,11 +594,10 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
         const double tY = double(dfy[v]) * b.inv_dx1;
         const double tZ = double(Fn[v] - Fo[v]) * b.inv_dx2;
         const double L = -((tX + tY) + tZ);
-        const double uin = double(Uin[o + v * vs]);
         if (STAGE == 1) {
-          unew[v] = uin + dt * L;
+          unew[v] = uo[v] + dt * L;
         } else {
-          unew[v] = 0.5 * double(a.Un[o + v * vs]) + 0.5 * (uin + dt * L);
+          unew[v] = 0.5 * un[v] + 0.5 * (uo[v] + dt * L);
         }
       }
 #pragma unroll
@@ -450,6 +606,7 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
         Fz[v] = Fk[v];
         aRz[v] = aRn[v];
       }
+      chk = chn;
       if (STAGE == 2 && a.smax) {
         double q[5];
 #pragma unroll
@@ -468,14 +625,19 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
   return smax;
 }
 
-template <class S, class R, int TX, int TY, int STAGE>
-__global__ __launch_bounds__(TX* TY) void stage_kernel(StageArgs<S, R> a) {
-  __shared__ HydroSmem<R, TX, TY> sm;
+// Single-box stage: 16 x 14 tiles on 256 threads, so that each sweep phase
+// (18 x 14 and 16 x 16 reconstructions, 17 x 14 and 16 x 15 faces) is one
+// item per thread.
+constexpr int STX = 16, STY = 14, SNT = 256;
+
+template <class S, class R, int STAGE>
+__global__ __launch_bounds__(SNT) void stage_kernel(StageArgs<S, R> a) {
+  __shared__ HydroSmem<R, STX, STY, true> sm;
   const TileId tl = tile_of_block(a.gx, a.gy);
   bool bad = false;
-  const double smax = stage_tile<S, R, TX, TY, STAGE>(a, tl.bx, tl.by, tl.bz, sm, bad);
+  const double smax = stage_tile<S, R, STX, STY, SNT, true, STAGE>(a, tl.bx, tl.by, tl.bz, sm, bad);
   if (bad) atomicOr(a.err, ERR_NEG);
-  if (STAGE == 2 && a.smax) block_max_to<TX * TY>(smax, a.smax);
+  if (STAGE == 2 && a.smax) block_max_to<SNT>(smax, a.smax);
 }
 
 

@@ -164,28 +164,43 @@ __device__ __forceinline__ void block_umax_to(uint32_t x, uint32_t* dst) {
   }
 }
 
-template <class R, int TX, int TY>
+// LDS of one radiation tile (SPLIT as for the hydro stage).
+template <class R, int TX, int TY, bool SPLIT>
 struct RadSmem {
-  static constexpr int NREC = ((TX + 2) * TY > TX * (TY + 2)) ? (TX + 2) * TY : TX * (TY + 2);
-  static constexpr int NFL = ((TX + 1) * TY > TX * (TY + 1)) ? (TX + 1) * TY : TX * (TY + 1);
+  static constexpr int NXR = (TX + 2) * TY, NYR = TX * (TY + 2);
+  static constexpr int NXF = (TX + 1) * TY, NYF = TX * (TY + 1);
+  static constexpr int XS = SPLIT ? NXR : (NXR > NYR ? NXR : NYR);
+  static constexpr int XFS = SPLIT ? NXF : (NXF > NYF ? NXF : NYF);
+  static constexpr int YS = SPLIT ? NYR : XS, YFS = SPLIT ? NYF : XFS;
   R Qp[4][TY + 6][TX + 6];
   R rhoP[TY + 2][TX + 2];
-  R recL[4][NREC];
-  R recR[4][NREC];
-  R fl[4][NFL];
+  R xL[4][XS], xR[4][XS];
+  R xF[4][XFS];
+  R yL[4][SPLIT ? NYR : 1], yR[4][SPLIT ? NYR : 1];
+  R yF[4][SPLIT ? NYF : 1];
 };
 
 // One tile of columns of one box for substep `a.sub` (the caller has checked
 // that the substep is active).  Returns the largest exchange iteration count.
-template <class S, class R, int TX, int TY, int STAGE>
+// NT threads (NT >= TX*TY); thread t owns column (t % TX, t / TX).
+template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE>
 __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tbx, int tby, int tbz, int N,
-                                             RadSmem<R, TX, TY>& sm, bool& bad_out, bool& nfail_out) {
-  constexpr int NT = TX * TY;
+                                             RadSmem<R, TX, TY, SPLIT>& sm, bool& bad_out, bool& nfail_out) {
+  using SM = RadSmem<R, TX, TY, SPLIT>;
+  constexpr int NXR = SM::NXR, NYR = SM::NYR, NXF = SM::NXF, NYF = SM::NYF;
+  constexpr int XS = SM::XS, YS = SM::YS, XFS = SM::XFS, YFS = SM::YFS;
+  constexpr int NHX = 6 * TY, NHY = 6 * TX, NCX = 2 * TY, NCY = 2 * TX;
+  constexpr int NH = NHX + NHY + NCX + NCY, HPT = (NH + NT - 1) / NT;
+  static_assert(NT >= TX * TY, "one thread per column");
+  R* const xL = &sm.xL[0][0];
+  R* const xR = &sm.xR[0][0];
+  R* const xF = &sm.xF[0][0];
+  R* const yL = SPLIT ? &sm.yL[0][0] : xL;
+  R* const yR = SPLIT ? &sm.yR[0][0] : xR;
+  R* const yF = SPLIT ? &sm.yF[0][0] : xF;
   auto& Qp = sm.Qp;
   auto& rhoP = sm.rhoP;
-  auto& recL = sm.recL;
-  auto& recR = sm.recR;
-  auto& fl = sm.fl;
+
   const DevBox& b = a.b;
   const RadParamsDev& p = a.p;
   const int t = threadIdx.x, tx = t % TX, ty = t / TX;
@@ -195,34 +210,76 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
   const int z1 = min(z0 + a.zc, b.n2);
   const bool act = tx < tw && ty < th;
   const int i = x0 + tx, j = y0 + ty;
-  const int64_t vs = b.vs;
+  const int64_t vs = b.vs, pz = b.pz;
   const double dt = (a.dt_ptr ? *a.dt_ptr : a.dt_val) / N;  // substep dt
   const R c = R(p.c), chat = R(p.chat), ratio = R(p.chat / p.c), cc = R(p.c * p.chat);
-  const R inv_c = R(1.0 / p.c);
   const bool tauc = p.tau_correction != 0;
   const S* __restrict__ Uin = a.Uin;
+  const S* __restrict__ Ug = a.Ug;
   bool bad = false, nfail = false;
   uint32_t itmax = 0;
+
+  // halo ring of every plane: 3 cells of (E, F) beyond each x and y edge of
+  // the tile, 1 cell of gas density (optical-depth factor only)
+  HaloCell<S> hc[HPT];
+#pragma unroll
+  for (int m = 0; m < HPT; ++m) {
+    const int it = t + m * NT;
+    int xx = 0, yy = 0, kind = 0;
+    if (it < NHX) {
+      const int c6 = it % 6;
+      yy = it / 6;
+      xx = c6 < 3 ? c6 - 3 : tw + c6 - 3;
+      kind = yy < th ? 1 : 0;
+    } else if (it < NHX + NHY) {
+      const int r = it - NHX, c6 = r / TX;
+      xx = r % TX;
+      yy = c6 < 3 ? c6 - 3 : th + c6 - 3;
+      kind = xx < tw ? 1 : 0;
+    } else if (it < NHX + NHY + NCX) {
+      const int r = it - NHX - NHY;
+      yy = r >> 1;
+      xx = (r & 1) ? tw : -1;
+      kind = (tauc && yy < th) ? 2 : 0;
+    } else if (it < NH) {
+      const int r = it - NHX - NHY - NCX;
+      xx = r % TX;
+      yy = (r / TX) ? th : -1;
+      kind = (tauc && xx < tw) ? 2 : 0;
+    }
+    hc[m].kind = kind;
+    hc[m].src = src_at(Uin, a.Ugh, b, x0 + xx, y0 + yy, z0);
+    hc[m].off = cell(b, x0 + xx, y0 + yy, 0);
+    hc[m].lds = kind == 2 ? (yy + 1) * (TX + 2) + (xx + 1) : (yy + 3) * (TX + 6) + (xx + 3);
+  }
 
   R w[4][5];  // own column (E, fx, fy, fz): [var][slot], slot s = plane m-2+s
   R aRz[4], Fz[4];
   R rz_k = R(0), rz_k1 = R(0);  // density of own column at k and k+1 (tau correction)
+  double cq[4];                 // own column, plane k+3 (prefetched)
+  double hq[HPT][4];            // halo ring of plane k (prefetched)
+  double uo[4], un0[4], gas[5];
 
-  auto load_q = [&](int ii, int jj, int kk, R* Q, bool& flag) {
-    const int64_t o = cell(b, ii, jj, kk);
-    const S* __restrict__ U = src_at(Uin, a.Ugh, b, ii, jj, kk);
-    const double E = double(U[o]);
+  // (E, F) -> (E, f = F / (c E))
+  auto to_q = [&](const double* u, R* Q, bool& flag) {
+    const double E = u[0];
     const R Er = R(E);
     const R inv = R(1) / (c * Er);
     Q[0] = Er;
-    Q[1] = R(U[o + vs]) * inv;
-    Q[2] = R(U[o + 2 * vs]) * inv;
-    Q[3] = R(U[o + 3 * vs]) * inv;
+    Q[1] = R(u[1]) * inv;
+    Q[2] = R(u[2]) * inv;
+    Q[3] = R(u[3]) * inv;
     flag = flag || !(E > 0.0);
   };
+  auto load4 = [&](const S* U, int64_t o, double* q) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) q[v] = double(U[o + v * vs]);
+  };
   auto load_w = [&](int kk, int slot) {
+    double q[4];
+    load4(src_at(Uin, a.Ugh, b, i, j, kk), cell(b, i, j, kk), q);
     R Q[4];
-    load_q(i, j, kk, Q, bad);
+    to_q(q, Q, bad);
 #pragma unroll
     for (int v = 0; v < 4; ++v) w[v][slot] = Q[v];
   };
@@ -237,11 +294,11 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
 #pragma unroll
     for (int v = 0; v < 4; ++v) recon5<R>(w[v][0], w[v][1], w[v][2], w[v][3], w[v][4], p.recon, L[v], Rr[v]);
   };
-  auto rho_at = [&](int kk) { return R(a.Ug[cell(b, i, j, kk)]); };
+  auto rho_at = [&](int kk) { return R(Ug[cell(b, i, j, kk)]); };
 
   // z prologue: flux through the bottom face of the chunk
-  R cprev[4];
   if (act) {
+    R cprev[4];
 #pragma unroll
     for (int s = 0; s < 5; ++s) load_w(z0 - 3 + s, s);
     R l[4], rprev[4];
@@ -263,122 +320,161 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
 #pragma unroll
     for (int v = 0; v < 4; ++v) aRz[v] = rcur[v];
     rz_k1 = rr;
+    load4(src_at(Uin, a.Ugh, b, i, j, z0 + 3), cell(b, i, j, z0 + 3), cq);
   }
+#pragma unroll
+  for (int m = 0; m < HPT; ++m) load_halo<4>(hc[m], hc[m].src, Ug, (int64_t)z0 * pz, vs, hq[m]);
   bad = false;
 
   for (int k = z0; k < z1; ++k) {
+    R rhn = R(0);
     if (act) {
       shift_w();
-      load_w(k + 3, 4);  // planes k-1..k+3, plane k in slot 1
+      R Q[4];
+      to_q(cq, Q, bad);  // planes k-1..k+3, plane k in slot 1
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Qp[v][ty + 3][tx + 3] = w[v][1];
+      for (int v = 0; v < 4; ++v) {
+        w[v][4] = Q[v];
+        Qp[v][ty + 3][tx + 3] = w[v][1];
+      }
       if (tauc) {
         rz_k = rz_k1;
-        rz_k1 = rho_at(k + 1);
         rhoP[ty + 1][tx + 1] = rz_k;
       }
     }
-    {
-      const int nxh = 6 * th, nyh = 6 * tw, nh = nxh + nyh;
-      const int nrx = tauc ? 2 * th : 0, nry = tauc ? 2 * tw : 0;
-      for (int it = t; it < nh + nrx + nry; it += NT) {
-        if (it < nh) {
-          int xx, yy;
-          if (it < nxh) {
-            const int cc6 = it % 6;
-            yy = it / 6;
-            xx = cc6 < 3 ? cc6 - 3 : tw + cc6 - 3;
-          } else {
-            const int r = it - nxh, cc6 = r / tw;
-            xx = r % tw;
-            yy = cc6 < 3 ? cc6 - 3 : th + cc6 - 3;
-          }
-          R Q[4];
-          bool dummy = false;
-          load_q(x0 + xx, y0 + yy, k, Q, dummy);
 #pragma unroll
-          for (int v = 0; v < 4; ++v) Qp[v][yy + 3][xx + 3] = Q[v];
-        } else if (it < nh + nrx) {
-          const int r = it - nh;
-          const int yy = r >> 1, xx = (r & 1) ? tw : -1;
-          rhoP[yy + 1][xx + 1] = R(a.Ug[cell(b, x0 + xx, y0 + yy, k)]);
-        } else {
-          const int r = it - nh - nrx;
-          const int xx = r % tw, yy = (r / tw) ? th : -1;
-          rhoP[yy + 1][xx + 1] = R(a.Ug[cell(b, x0 + xx, y0 + yy, k)]);
+    for (int m = 0; m < HPT; ++m) {
+      if (hc[m].kind == 1) {
+        R Q[4];
+        bool dummy = false;
+        to_q(hq[m], Q, dummy);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) (&Qp[v][0][0])[hc[m].lds] = Q[v];
+      } else if (hc[m].kind == 2) {
+        (&rhoP[0][0])[hc[m].lds] = R(hq[m][0]);
+      }
+    }
+    // loads for the rest of this plane and the next one, in flight during the sweeps
+    if (act) {
+      const int64_t o = cell(b, i, j, k);
+      if (tauc) rhn = R(Ug[o + pz]);
+      load4(Uin, o, uo);
+      if (STAGE == 2) {
+        load4(a.Un, o, un0);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) gas[v] = double(Ug[o + v * vs]);
+      }
+      if (k + 1 < z1) load4(src_at(Uin, a.Ugh, b, i, j, k + 4), o + 4 * pz, cq);
+    }
+    if (k + 1 < z1) {
+#pragma unroll
+      for (int m = 0; m < HPT; ++m) load_halo<4>(hc[m], hc[m].src, Ug, (int64_t)(k + 1) * pz, vs, hq[m]);
+    }
+    __syncthreads();
+
+    auto x_recon = [&]() {
+      for (int it = t; it < NXR; it += NT) {
+        const int xx = it % (TX + 2) - 1, yy = it / (TX + 2);
+        if (xx <= tw && yy < th) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const R* row = &Qp[v][yy + 3][xx + 1];
+            recon5<R>(row[0], row[1], row[2], row[3], row[4], p.recon, xL[v * XS + it], xR[v * XS + it]);
+          }
         }
       }
-    }
-    __syncthreads();
+    };
+    auto x_faces = [&]() {
+      for (int it = t; it < NXF; it += NT) {
+        const int fx = it % (TX + 1), yy = it / (TX + 1);
+        if (fx <= tw && yy < th) {
+          const int il = yy * (TX + 2) + fx, ir = il + 1;
+          R sl[4], sr[4], cl[4], cr[4], F[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            sl[v] = xR[v * XS + il];
+            sr[v] = xL[v * XS + ir];
+            cl[v] = Qp[v][yy + 3][fx + 2];
+            cr[v] = Qp[v][yy + 3][fx + 3];
+          }
+          const R rl = tauc ? rhoP[yy + 1][fx] : R(0), rr = tauc ? rhoP[yy + 1][fx + 1] : R(0);
+          rad_face<R>(sl, sr, cl, cr, rl, rr, R(b.dx0), 0, p, c, chat, ratio, cc, F);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) xF[v * XFS + it] = F[v];
+        }
+      }
+    };
+    auto y_recon = [&]() {
+      for (int it = t; it < NYR; it += NT) {
+        const int xx = it % TX, yy = it / TX - 1;
+        if (xx < tw && yy <= th) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            recon5<R>(Qp[v][yy + 1][xx + 3], Qp[v][yy + 2][xx + 3], Qp[v][yy + 3][xx + 3], Qp[v][yy + 4][xx + 3],
+                      Qp[v][yy + 5][xx + 3], p.recon, yL[v * YS + it], yR[v * YS + it]);
+        }
+      }
+    };
+    auto y_faces = [&]() {
+      for (int it = t; it < NYF; it += NT) {
+        const int xx = it % TX, fy = it / TX;
+        if (xx < tw && fy <= th) {
+          const int il = fy * TX + xx, ir = il + TX;
+          R sl[4], sr[4], cl[4], cr[4], F[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            sl[v] = yR[v * YS + il];
+            sr[v] = yL[v * YS + ir];
+            cl[v] = Qp[v][fy + 2][xx + 3];
+            cr[v] = Qp[v][fy + 3][xx + 3];
+          }
+          const R rl = tauc ? rhoP[fy][xx + 1] : R(0), rr = tauc ? rhoP[fy + 1][xx + 1] : R(0);
+          rad_face<R>(sl, sr, cl, cr, rl, rr, R(b.dx1), 1, p, c, chat, ratio, cc, F);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) yF[v * YFS + it] = F[v];
+        }
+      }
+    };
 
-    // ---- x sweep
-    for (int it = t; it < (tw + 2) * th; it += NT) {
-      const int xx = it % (tw + 2) - 1, yy = it / (tw + 2);
+    R dfx[4], dfy[4];
+    if constexpr (SPLIT) {
+      x_recon();
+      y_recon();
+      __syncthreads();
+      x_faces();
+      y_faces();
+      __syncthreads();
+      if (act) {
+        const int fxi = ty * (TX + 1) + tx, fyi = ty * TX + tx;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const R* row = &Qp[v][yy + 3][xx + 1];
-        recon5<R>(row[0], row[1], row[2], row[3], row[4], p.recon, recL[v][it], recR[v][it]);
+        for (int v = 0; v < 4; ++v) {
+          dfx[v] = xF[v * XFS + fxi + 1] - xF[v * XFS + fxi];
+          dfy[v] = yF[v * YFS + fyi + TX] - yF[v * YFS + fyi];
+        }
+      }
+    } else {
+      x_recon();
+      __syncthreads();
+      x_faces();
+      __syncthreads();
+      if (act) {
+        const int fxi = ty * (TX + 1) + tx;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dfx[v] = xF[v * XFS + fxi + 1] - xF[v * XFS + fxi];
+      }
+      y_recon();
+      __syncthreads();
+      y_faces();
+      __syncthreads();
+      if (act) {
+        const int fyi = ty * TX + tx;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dfy[v] = yF[v * YFS + fyi + TX] - yF[v * YFS + fyi];
       }
     }
-    __syncthreads();
-    for (int it = t; it < (tw + 1) * th; it += NT) {
-      const int fx = it % (tw + 1), yy = it / (tw + 1);
-      const int il = yy * (tw + 2) + fx, ir = il + 1;
-      R sl[4], sr[4], cl[4], cr[4], F[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        sl[v] = recR[v][il];
-        sr[v] = recL[v][ir];
-        cl[v] = Qp[v][yy + 3][fx + 2];
-        cr[v] = Qp[v][yy + 3][fx + 3];
-      }
-      const R rl = tauc ? rhoP[yy + 1][fx] : R(0), rr = tauc ? rhoP[yy + 1][fx + 1] : R(0);
-      rad_face<R>(sl, sr, cl, cr, rl, rr, R(b.dx0), 0, p, c, chat, ratio, cc, F);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) fl[v][it] = F[v];
-    }
-    __syncthreads();
-    R dfx[4];
+
     if (act) {
-      const int f = ty * (tw + 1) + tx;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) dfx[v] = fl[v][f + 1] - fl[v][f];
-    }
-
-    // ---- y sweep
-    for (int it = t; it < tw * (th + 2); it += NT) {
-      const int xx = it % tw, yy = it / tw - 1;
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        recon5<R>(Qp[v][yy + 1][xx + 3], Qp[v][yy + 2][xx + 3], Qp[v][yy + 3][xx + 3], Qp[v][yy + 4][xx + 3],
-                  Qp[v][yy + 5][xx + 3], p.recon, recL[v][it], recR[v][it]);
-    }
-    __syncthreads();
-    for (int it = t; it < tw * (th + 1); it += NT) {
-      const int xx = it % tw, fy = it / tw;
-      const int il = fy * tw + xx, ir = il + tw;
-      R sl[4], sr[4], cl[4], cr[4], F[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        sl[v] = recR[v][il];
-        sr[v] = recL[v][ir];
-        cl[v] = Qp[v][fy + 2][xx + 3];
-        cr[v] = Qp[v][fy + 3][xx + 3];
-      }
-      const R rl = tauc ? rhoP[fy][xx + 1] : R(0), rr = tauc ? rhoP[fy + 1][xx + 1] : R(0);
-      rad_face<R>(sl, sr, cl, cr, rl, rr, R(b.dx1), 1, p, c, chat, ratio, cc, F);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) fl[v][it] = F[v];
-    }
-    __syncthreads();
-
-    if (act) {
-      R dfy[4];
-      {
-        const int f = ty * tw + tx;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) dfy[v] = fl[v][f + tw] - fl[v][f];
-      }
+      if (tauc) rz_k1 = rhn;
       // ---- z sweep: cell k+1 centred in the window
       R aLn[4], aRn[4], Fk[4], ck[4], ck1[4];
       recon_z(aLn, aRn);
@@ -396,15 +492,11 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
         const double tY = double(dfy[v]) * b.inv_dx1;
         const double tZ = double(Fk[v] - Fz[v]) * b.inv_dx2;
         const double L = -((tX + tY) + tZ);
-        const double uin = double(Uin[o + v * vs]);
-        un[v] = (STAGE == 1) ? uin + dt * L : 0.5 * double(a.Un[o + v * vs]) + 0.5 * (uin + dt * L);
+        un[v] = (STAGE == 1) ? uo[v] + dt * L : 0.5 * un0[v] + 0.5 * (uo[v] + dt * L);
         Fz[v] = Fk[v];
         aRz[v] = aRn[v];
       }
       if (STAGE == 2) {
-        double gas[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) gas[v] = double(a.Ug[o + v * vs]);
         const int it = exchange(p, dt, gas, un, nfail);
         itmax = max(itmax, (uint32_t)it);
 #pragma unroll
@@ -417,21 +509,20 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
   }
   bad_out = bad_out || bad;
   nfail_out = nfail_out || nfail;
-  (void)inv_c;
   return itmax;
 }
 
-template <class S, class R, int TX, int TY, int STAGE>
-__global__ __launch_bounds__(TX* TY, 2) void rad_stage_kernel(RadStageArgs<S, R> a) {
+template <class S, class R, int STAGE>
+__global__ __launch_bounds__(SNT, 2) void rad_stage_kernel(RadStageArgs<S, R> a) {
   const int N = a.nsub_ptr ? *a.nsub_ptr : a.nsub_val;
   if (a.sub >= N) return;  // block-uniform: the whole grid skips unused substeps
-  __shared__ RadSmem<R, TX, TY> sm;
+  __shared__ RadSmem<R, STX, STY, true> sm;
   const TileId tl = tile_of_block(a.gx, a.gy);
   bool bad = false, nfail = false;
-  const uint32_t itmax = rad_tile<S, R, TX, TY, STAGE>(a, tl.bx, tl.by, tl.bz, N, sm, bad, nfail);
+  const uint32_t itmax = rad_tile<S, R, STX, STY, SNT, true, STAGE>(a, tl.bx, tl.by, tl.bz, N, sm, bad, nfail);
   if (bad) atomicOr(a.err, ERR_NEG);
   if (nfail) atomicOr(a.err, ERR_NEWTON);
-  if (STAGE == 2) block_umax_to<TX * TY>(itmax, a.iter_max);
+  if (STAGE == 2) block_umax_to<SNT>(itmax, a.iter_max);
 }
 
 
