@@ -240,22 +240,43 @@ void launch_ghost_copy(const HostBox& hb, S* dst, const S* src, int nvar, hipStr
   hipLaunchKernelGGL(ghost_copy_kernel<S>, dim3(grid_for(total, 256, 8192)), dim3(256), 0, s, dst, src, d, nvar);
 }
 
-// Tile shape of the flattening pass for one box (the stage uses STX x STY).
-constexpr int HTX = 16, HTY = 16;
-
 struct Launch {
   int gx, gy, gz, zc;
 };
 
-Launch plan(int n0, int n1, int n2, int tx, int ty, int target_blocks) {
+// Blocks of `kernel` resident on the whole device at once (occupancy x CUs).
+template <class K>
+int resident_grid(K kernel, int threads) {
+  int dev = 0, ncu = 0, per = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1) per = 1;
+  return std::max(1, ncu) * per;
+}
+
+// Column tiles of tx x ty and the z chunk per block.  Blocks run in
+// "generations" of `resident` at a time; the chunk count c minimises
+// generations x (planes per chunk + the chunk's z prologue, ~2.5 planes),
+// with at least 8 planes per chunk, so that the last generation is not a
+// nearly empty one.
+Launch plan(int n0, int n1, int n2, int tx, int ty, int resident) {
   Launch L;
   L.gx = (n0 + tx - 1) / tx;
   L.gy = (n1 + ty - 1) / ty;
-  const int nxy = L.gx * L.gy;
-  int chunks = std::max(1, std::min(n2, (target_blocks + nxy - 1) / nxy));
-  // keep at least 8 planes per chunk so the z prologue stays a small fraction
-  chunks = std::max(1, std::min(chunks, std::max(1, n2 / 8)));
-  L.zc = (n2 + chunks - 1) / chunks;
+  const int64_t nxy = (int64_t)L.gx * L.gy;
+  const int cmax = std::max(1, n2 / 8);
+  double best = 1e300;
+  int bc = 1;
+  for (int c = 1; c <= cmax; ++c) {
+    const int zc = (n2 + c - 1) / c, gz = (n2 + zc - 1) / zc;
+    const int64_t gens = (nxy * gz + resident - 1) / std::max(1, resident);
+    const double cost = (double)gens * (zc + 2.5);
+    if (cost < best - 1e-9) {
+      best = cost;
+      bc = c;
+    }
+  }
+  L.zc = (n2 + bc - 1) / bc;
   L.gz = (n2 + L.zc - 1) / L.zc;
   return L;
 }
@@ -263,7 +284,8 @@ Launch plan(int n0, int n1, int n2, int tx, int ty, int target_blocks) {
 template <class S, class R>
 void launch_flatten(const HostBox& hb, const S* U, R* chi, double gamma, hipStream_t s) {
   const DevBox& d = hb.d;
-  Launch L = plan(d.n0 + 2, d.n1 + 2, d.n2 + 2, HTX, HTY, 2048);
+  static const int res = resident_grid(flatten_kernel<S, R>, FNT);
+  Launch L = plan(d.n0 + 2, d.n1 + 2, d.n2 + 2, FTX, FTY, res);
   FlatArgs<S, R> a;
   a.U = U;
   a.Ugh = nullptr;
@@ -271,8 +293,7 @@ void launch_flatten(const HostBox& hb, const S* U, R* chi, double gamma, hipStre
   a.b = d;
   a.gm1 = gamma - 1.0;
   a.zc = L.zc;
-  hipLaunchKernelGGL((flatten_kernel<S, R, HTX, HTY>), dim3(L.gx * L.gy * L.gz), dim3(HTX * HTY), 0, s, a, L.gx,
-                     L.gy);
+  hipLaunchKernelGGL((flatten_kernel<S, R>), dim3(L.gx * L.gy * L.gz), dim3(FNT), 0, s, a, L.gx, L.gy);
 }
 
 template <class S, class R, int STAGE>
@@ -280,7 +301,8 @@ void launch_stage(const HostBox& hb, const S* Uin, const S* Un, S* Uout, const R
                   const double* dt_ptr, double dt_val, unsigned long long* smax, uint32_t* err, int recon,
                   hipStream_t s) {
   const DevBox& d = hb.d;
-  Launch L = plan(d.n0, d.n1, d.n2, STX, STY, 2048);
+  static const int res = resident_grid(stage_kernel<S, R, STAGE>, SNT);
+  Launch L = plan(d.n0, d.n1, d.n2, STX, STY, res);
   StageArgs<S, R> a;
   a.Uin = Uin;
   a.Ugh = nullptr;

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(TX* TY) void batch_flatten_kernel(const BatchBox<S,
     a.b = bb.b;
     a.gm1 = bb.gamma - 1.0;
     a.zc = bb.zc_flat;
-    flatten_tile<S, R, TX, TY>(a, w.bx, w.by, w.bz, sm);
+    flatten_tile<S, R, TX, TY, TX * TY>(a, w.bx, w.by, w.bz, sm);
   }
 }
 

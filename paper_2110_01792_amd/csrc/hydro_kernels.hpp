@@ -40,13 +40,15 @@ struct StageArgs {
 // 1-D launch: consecutive hardware blocks are dealt round-robin to the 8
 // XCDs, each with its own L2.  Re-number them so that every XCD receives one
 // contiguous range of tiles (x fastest, then y, then z chunk): neighbouring
-// tiles, which share halo planes, then run under the same L2.
+// tiles, which share halo planes, then run under the same L2.  XCD x holds
+// blocks x, x+8, ...: nb/8 of them, one more for the first nb%8 XCDs.
 struct TileId {
   int bx, by, bz;
 };
 __device__ __forceinline__ TileId tile_of_block(int gx, int gy) {
   const int hw = (int)blockIdx.x, nb = (int)gridDim.x;
-  const int lg = (nb % 8 == 0) ? (hw % 8) * (nb / 8) + hw / 8 : hw;
+  const int x = hw % 8, q = nb / 8, r = nb % 8;
+  const int lg = x * q + min(x, r) + hw / 8;
   TileId t;
   t.bx = lg % gx;
   t.by = (lg / gx) % gy;
@@ -131,11 +133,12 @@ __device__ __forceinline__ void load_halo(const HaloCell<S>& h, const S* src, co
 
 // One tile of columns (tile indices over the grown range [-1, n]).  The
 // tile's own cells come from each thread's z window; the 3-cell halo ring of
-// each plane is prefetched one plane ahead into registers.
-template <class S, class R, int TX, int TY>
+// each plane is prefetched one plane ahead into registers.  NT threads
+// (NT >= TX*TY); thread t owns column (t % TX, t / TX).
+template <class S, class R, int TX, int TY, int NT>
 __device__ __forceinline__ void flatten_tile(const FlatArgs<S, R>& a, int tbx, int tby, int tbz,
                                              FlatSmem<R, TX, TY>& sm) {
-  constexpr int NT = TX * TY;
+  static_assert(NT >= TX * TY, "one thread per column");
   constexpr int NHX = 6 * TY, NHY = 6 * TX, NH = NHX + NHY, HPT = (NH + NT - 1) / NT;
   const DevBox& b = a.b;
   const int t = threadIdx.x, tx = t % TX, ty = t / TX;
@@ -277,11 +280,15 @@ __device__ __forceinline__ void flatten_tile(const FlatArgs<S, R>& a, int tbx, i
   }
 }
 
-template <class S, class R, int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void flatten_kernel(FlatArgs<S, R> a, int gx, int gy) {
-  __shared__ FlatSmem<R, TX, TY> sm;
+// Single-box flattening: 16 x 14 tiles on 256 threads (each phase one item
+// per thread, as in the stage).
+constexpr int FTX = 16, FTY = 14, FNT = 256;
+
+template <class S, class R>
+__global__ __launch_bounds__(FNT) void flatten_kernel(FlatArgs<S, R> a, int gx, int gy) {
+  __shared__ FlatSmem<R, FTX, FTY> sm;
   const TileId tl = tile_of_block(gx, gy);
-  flatten_tile<S, R, TX, TY>(a, tl.bx, tl.by, tl.bz, sm);
+  flatten_tile<S, R, FTX, FTY, FNT>(a, tl.bx, tl.by, tl.bz, sm);
 }
 
 // ---------------------------------------------------------------------------

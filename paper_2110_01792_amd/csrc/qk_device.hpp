@@ -151,13 +151,18 @@ __device__ __forceinline__ void cons_to_prim(double rho, double mx, double my, d
 // Flattening coefficient of one cell along one axis before the neighbour
 // minimum (Miller & Colella 2002 generalising CW84; CW84 constants).
 // p* are pressures at offsets -2..+2, u* the axis velocity at -1, +1.
+// The ratio and ramp (two divisions) are formed only where the shock test
+// holds: away from shocks whole waves skip them.
 template <class R>
 __device__ __forceinline__ R chi_tilde(R pm2, R pm1, R pp1, R pp2, R um1, R up1) {
   const R dp1 = pp1 - pm1, dp2 = pp2 - pm2, du = up1 - um1;
   const bool shock = (fabs(dp1) > R(0.33) * rmin(pp1, pm1)) && (du < R(0));
-  const R z = fabs(dp1) / rmax(fabs(dp2), R(1e-300));
-  const R t = rmin(R(1), rmax(R(0), R(1) - (z - R(0.75)) / (R(0.85) - R(0.75))));
-  return shock ? t : R(1);
+  R t = R(1);
+  if (shock) {
+    const R z = fabs(dp1) / rmax(fabs(dp2), R(1e-300));
+    t = rmin(R(1), rmax(R(0), R(1) - (z - R(0.75)) / (R(0.85) - R(0.75))));
+  }
+  return t;
 }
 
 // float cannot hold 1e-300; the floor only guards a 0/0 when both pressure
@@ -166,9 +171,12 @@ template <>
 __device__ __forceinline__ float chi_tilde<float>(float pm2, float pm1, float pp1, float pp2, float um1, float up1) {
   const float dp1 = pp1 - pm1, dp2 = pp2 - pm2, du = up1 - um1;
   const bool shock = (fabsf(dp1) > 0.33f * fminf(pp1, pm1)) && (du < 0.0f);
-  const float z = fabsf(dp1) / fmaxf(fabsf(dp2), 1e-30f);
-  const float t = fminf(1.0f, fmaxf(0.0f, 1.0f - (z - 0.75f) / (0.85f - 0.75f)));
-  return shock ? t : 1.0f;
+  float t = 1.0f;
+  if (shock) {
+    const float z = fabsf(dp1) / fmaxf(fabsf(dp2), 1e-30f);
+    t = fminf(1.0f, fmaxf(0.0f, 1.0f - (z - 0.75f) / (0.85f - 0.75f)));
+  }
+  return t;
 }
 
 // ---------------------------------------------------------------------------
