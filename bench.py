@@ -52,8 +52,8 @@ def timed_steps(step, k, torch):
     return e0.elapsed_time(e1)
 
 
-def bench_hydro(ctx, qb, inputs, torch, steps, warmup, dtype):
-    b, U, p = inputs.hydro_shock(n=256)
+def bench_hydro(ctx, qb, inputs, torch, steps, warmup, dtype, workload="shock"):
+    b, U, p = inputs.hydro_shock(n=256) if workload == "shock" else inputs.sedov(n=256)
     Ud = torch.from_numpy(U).to(dtype).cuda()
     del U
     ctx.fill_ghosts(b, Ud)
@@ -85,6 +85,8 @@ def bench_hydro(ctx, qb, inputs, torch, steps, warmup, dtype):
         "stage_launches": nst,
         "ncells": ncell,
     }
+    # whole step against HBM: algorithmic bytes per cell-update x updates/s
+    out["step_hbm_frac"] = HYDRO_BYTES_PER_CELL_STEP * scale * out["cell_updates_per_s"] / (HBM_PEAK_GBS * 1e9)
     # algorithmic bytes per stage launch: average of the two stages
     bytes_per_launch = ncell * HYDRO_BYTES_PER_CELL_STEP * scale / 2.0
     out["stage_achieved_GBs"] = bytes_per_launch / (out["stage_ms_avg"] * 1e-3) / 1e9
@@ -98,8 +100,12 @@ RAD_BYTES_STAGE1 = 72.0    # read E_r, F (32) + density (8), write 32   (FP64, p
 RAD_BYTES_STAGE2 = 168.0   # read Ur1, Ur (64) + gas (40), write Ur (32) + m, E (32)
 
 
-def bench_rhd(ctx, qb, inputs, torch, steps, warmup, dtype, n=256):
+RHD_BYTES_PER_CELL_STEP = HYDRO_BYTES_PER_CELL_STEP + 10 * (RAD_BYTES_STAGE1 + RAD_BYTES_STAGE2)
+
+
+def bench_rhd(ctx, qb, inputs, torch, steps, warmup, dtype, n=256, recon=0):
     b, Ug, Ur, p = inputs.rhd_lognormal(n=n)
+    p = dict(p, recon=recon)
     G = torch.from_numpy(Ug).to(dtype).cuda()
     R = torch.from_numpy(Ur).to(dtype).cuda()
     del Ug, Ur
@@ -125,7 +131,8 @@ def bench_rhd(ctx, qb, inputs, torch, steps, warmup, dtype, n=256):
     out = {"ms_per_step": ms / steps, "cell_updates_per_s": ncell * steps / (ms * 1e-3), "status": int(st),
            "rad_stage1_ms_avg": r1_ms / max(n1, 1), "rad_stage2_couple_ms_avg": r2_ms / max(n2, 1),
            "hydro_stage_ms_avg": hs_ms / max(nh, 1), "launches": [n1, n2, nh], "newton_iter_max": it,
-           "ncells": ncell}
+           "ncells": ncell, "reconstruction": "PLM" if recon == 1 else "PPM"}
+    out["step_hbm_frac"] = RHD_BYTES_PER_CELL_STEP * scale * out["cell_updates_per_s"] / (HBM_PEAK_GBS * 1e9)
     out["rad_stage1_achieved_GBs"] = ncell * RAD_BYTES_STAGE1 * scale / (out["rad_stage1_ms_avg"] * 1e-3) / 1e9
     out["rad_stage2_achieved_GBs"] = ncell * RAD_BYTES_STAGE2 * scale / (out["rad_stage2_couple_ms_avg"] * 1e-3) / 1e9
     del G, R
@@ -235,8 +242,12 @@ def run_only(args, torch, qb, inputs):
     f64, f32 = torch.float64, torch.float32
     if args.only in ("hydro", "hydro32"):
         out, _, _ = bench_hydro(ctx, qb, inputs, torch, args.steps, args.warmup, f64 if args.only == "hydro" else f32)
+    elif args.only == "sedov":
+        out, _, _ = bench_hydro(ctx, qb, inputs, torch, args.steps, args.warmup, f64, workload="sedov")
     elif args.only in ("rhd", "rhd32"):
         out = bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, f64 if args.only == "rhd" else f32)
+    elif args.only == "rhdplm":
+        out = bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, f64, recon=1)
     else:
         out = bench_batch(ctx, qb, inputs, torch, args.steps, f64)
     ctx.close()
@@ -249,7 +260,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--only", default="all", choices=["all", "hydro", "rhd", "hydro32", "rhd32", "batch", "copy"],
+    ap.add_argument("--only", default="all", choices=["all", "hydro", "rhd", "hydro32", "rhd32", "sedov", "rhdplm", "batch", "copy"],
                     help="run one section only (for profiler runs); 'copy' runs a plain 2 GiB device copy used "
                          "to calibrate the HBM byte counters")
     args = ap.parse_args()
@@ -272,6 +283,11 @@ def main():
     log("RHD FP64 256^3 ...")
     r64 = bench_rhd(ctx, qb, inputs, torch, max(2, args.steps // 4), max(1, args.warmup // 2), torch.float64)
     log("RHD FP64:", r64)
+    log("paper workloads: Sedov 256^3 PPM hydro, RHD 256^3 PLM ...")
+    sed64, _, _ = bench_hydro(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float64, workload="sedov")
+    plm64 = bench_rhd(ctx, qb, inputs, torch, max(2, args.steps // 4), max(1, args.warmup // 2), torch.float64,
+                      recon=1)
+    log("Sedov:", sed64, "RHD PLM:", plm64)
     log("mixed ...")
     h32, _, _ = bench_hydro(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float32)
     r32 = bench_rhd(ctx, qb, inputs, torch, max(2, args.steps // 4), max(1, args.warmup // 2), torch.float32)
@@ -322,6 +338,15 @@ def main():
         "rhd_f64": dict(r64, workload="RHD FP64 256^3 periodic, log-normal density, T_gas and T_rad U[0.5,2], "
                                        "chat = 10 max c_s, kappa 1, Levermore, Newton tol 1e-12; one step = hydro "
                                        "RK2 + 10 radiation RK2 substeps + coupling"),
+        "paper_workloads": {
+            "sedov_ppm_f64": dict(sed64, workload="Sedov blast 256^3 periodic, rho 1, P 10 in r < 0.1 else 0.1, "
+                                                   "gamma 5/3, CFL 0.25, PPM (the paper's hydro performance "
+                                                   "problem)",
+                                  paper_context="113.34 Mzones/s V100, 254.05 Mzones/s A100 (PPM, 128^3 boxes)"),
+            "rhd_plm_f64": dict(plm64, workload="RHD FP64 256^3 as rhd_f64 with PLM for hydro and radiation",
+                                paper_context="22.55 Mzones/s V100, 39.04 Mzones/s A100 (PLM, radiation-driven "
+                                              "shell 256^3, 10 substeps)"),
+        },
         "hydro_mixed": h32,
         "rhd_mixed": r32,
         "batch_f64": b64,

@@ -189,13 +189,13 @@ __device__ __forceinline__ R closure_chi(R f2, int closure) {
   return closure == 1 ? R(1.0 / 3.0) : (R(3) + R(4) * f2) / (R(5) + R(2) * sqrt(R(4) - R(3) * f2));
 }
 
-// Row `d` of the Eddington tensor P/E and the HLL speed factor sqrt(P_dd/E).
-// Cartesian components of f are fx, fy, fz; f itself may exceed 1 only in
-// fallback states, where the closure uses min(|f|, 1) (Section 2.2.2).
+// Row `d` of the Eddington tensor P/E; Tdd = P_dd/E (the HLL speed is
+// chat sqrt(Tdd)).  Cartesian components of f are fx, fy, fz and fn = |f|;
+// f may exceed 1 only in fallback states, where the closure uses
+// min(|f|, 1) (Section 2.2.2).
 template <class R>
-__device__ __forceinline__ void eddington_row(R fx, R fy, R fz, int d, int closure, R& Tx, R& Ty, R& Tz, R& sd) {
-  const R f2raw = (fx * fx + fy * fy) + fz * fz;
-  const R fn = sqrt(f2raw);
+__device__ __forceinline__ void eddington_row(R fx, R fy, R fz, R fn, int d, int closure, R& Tx, R& Ty, R& Tz,
+                                              R& Tdd) {
   const R fh = rmin(fn, R(1));
   const R chi = closure_chi(fh * fh, closure);
   const R a = R(0.5) * (R(1) - chi);
@@ -208,8 +208,7 @@ __device__ __forceinline__ void eddington_row(R fx, R fy, R fz, int d, int closu
   Tx = bn * nx + (d == 0 ? a : R(0));
   Ty = bn * ny + (d == 1 ? a : R(0));
   Tz = bn * nz + (d == 2 ? a : R(0));
-  const R Tdd = d == 0 ? Tx : (d == 1 ? Ty : Tz);
-  sd = sqrt(Tdd);
+  Tdd = d == 0 ? Tx : (d == 1 ? Ty : Tz);
 }
 
 struct RadConst {

@@ -39,14 +39,17 @@ struct RadStageArgs {
   uint32_t* iter_max;
 };
 
-// HLL flux of (E, F) along axis d between face states (E, f) (Section 2.2.2).
+// HLL flux of (E, F) along axis d between face states (E, f), |f| = nL, nR
+// (Section 2.2.2).  The wave speed chat max(sqrt(T_dd^L), sqrt(T_dd^R)) is
+// formed as chat sqrt(max(T_dd^L, T_dd^R)) (sqrt is monotone and correctly
+// rounded: the same value).
 template <class R>
-__device__ __forceinline__ void rad_flux(R EL, R fLx, R fLy, R fLz, R ER, R fRx, R fRy, R fRz, int d, int closure,
-                                         R c, R chat, R ratio, R cc, R eps, R* out) {
-  R TLx, TLy, TLz, sL, TRx, TRy, TRz, sR;
-  eddington_row<R>(fLx, fLy, fLz, d, closure, TLx, TLy, TLz, sL);
-  eddington_row<R>(fRx, fRy, fRz, d, closure, TRx, TRy, TRz, sR);
-  const R S = chat * rmax(sL, sR);
+__device__ __forceinline__ void rad_flux(R EL, R fLx, R fLy, R fLz, R nL, R ER, R fRx, R fRy, R fRz, R nR, int d,
+                                         int closure, R c, R chat, R ratio, R cc, R eps, R* out) {
+  R TLx, TLy, TLz, dL, TRx, TRy, TRz, dR;
+  eddington_row<R>(fLx, fLy, fLz, nL, d, closure, TLx, TLy, TLz, dL);
+  eddington_row<R>(fRx, fRy, fRz, nR, d, closure, TRx, TRy, TRz, dR);
+  const R S = chat * sqrt(rmax(dL, dR));
   const R cEL = c * EL, cER = c * ER;
   const R FLx = cEL * fLx, FLy = cEL * fLy, FLz = cEL * fLz;
   const R FRx = cER * fRx, FRy = cER * fRy, FRz = cER * fRz;
@@ -65,8 +68,8 @@ __device__ __forceinline__ void rad_flux(R EL, R fLx, R fLy, R fLz, R ER, R fRx,
 template <class R>
 __device__ __forceinline__ void rad_face(const R* sl, const R* sr, const R* cl, const R* cr, R rhol, R rhor, R dxd,
                                          int d, const RadParamsDev& p, R c, R chat, R ratio, R cc, R* out) {
-  const R nl = sqrt((sl[1] * sl[1] + sl[2] * sl[2]) + sl[3] * sl[3]);
-  const R nr = sqrt((sr[1] * sr[1] + sr[2] * sr[2]) + sr[3] * sr[3]);
+  R nl = sqrt((sl[1] * sl[1] + sl[2] * sl[2]) + sl[3] * sl[3]);
+  R nr = sqrt((sr[1] * sr[1] + sr[2] * sr[2]) + sr[3] * sr[3]);
   const bool fb = (nl > R(1)) || (nr > R(1));
   R L[4], Rr[4];
 #pragma unroll
@@ -74,12 +77,16 @@ __device__ __forceinline__ void rad_face(const R* sl, const R* sr, const R* cl, 
     L[v] = fb ? cl[v] : sl[v];
     Rr[v] = fb ? cr[v] : sr[v];
   }
+  if (fb) {  // rare: whole waves skip the norms of the cell averages
+    nl = sqrt((cl[1] * cl[1] + cl[2] * cl[2]) + cl[3] * cl[3]);
+    nr = sqrt((cr[1] * cr[1] + cr[2] * cr[2]) + cr[3] * cr[3]);
+  }
   R eps = R(1);
   if (p.tau_correction) {
     const R tau = dxd * R(p.kappa_R) * (R(0.5) * (rhol + rhor));
     eps = fb ? R(1) : rmin(R(1), R(1) / tau);
   }
-  rad_flux<R>(L[0], L[1], L[2], L[3], Rr[0], Rr[1], Rr[2], Rr[3], d, p.closure, c, chat, ratio, cc, eps, out);
+  rad_flux<R>(L[0], L[1], L[2], L[3], nl, Rr[0], Rr[1], Rr[2], Rr[3], nr, d, p.closure, c, chat, ratio, cc, eps, out);
 }
 
 // Matter-radiation coupling of one cell (Section 2.2.3), FP64 throughout.
