@@ -89,6 +89,14 @@ typedef struct {
   int32_t eos;            /* 0: P = rho T, E_g = rho T/(gamma-1); 1: alpha T^4 */
   int32_t reconstruction; /* 0 PPM, 1 PLM, for E_r and f (Section 2.2.2) and, in
                              quokka_rhd_step, for the hydro step as well       */
+  const void* source;     /* NULL, or a DEVICE array of the radiation energy
+                             source rate j per cell (one variable in the box's
+                             layout and precision: pitch_y, pitch_z; ghosts
+                             unused; caller-owned).  Each coupling update adds
+                             S = dt_sub * j, the optional source term of
+                             Section 2.2.3, to the radiation residual and to
+                             the convergence scale E_tot.  Must be NULL for
+                             quokka_batch_step (QK_EINVAL otherwise).         */
 } qk_rad_params;
 
 /* Create a context on HIP device `device` (its scratch, device error word and

@@ -32,7 +32,8 @@ class _Rad(ctypes.Structure):
                 ("kappa_P", ctypes.c_double), ("kappa_R", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("alpha_cv", ctypes.c_double), ("cfl", ctypes.c_double), ("newton_tol", ctypes.c_double),
                 ("newton_max_iter", ctypes.c_int32), ("nsub_max", ctypes.c_int32), ("closure", ctypes.c_int32),
-                ("tau_correction", ctypes.c_int32), ("eos", ctypes.c_int32), ("recon", ctypes.c_int32)]
+                ("tau_correction", ctypes.c_int32), ("eos", ctypes.c_int32), ("recon", ctypes.c_int32),
+                ("src", ctypes.POINTER(ctypes.c_double))]
 
 
 class _Stats(ctypes.Structure):
@@ -60,10 +61,10 @@ def _load():
                                      P(_Stats)]),
         "oracle_rad_rhs": (None, [P(_Box), _D, _D, P(_Rad), _D, P(_Stats)]),
         "oracle_rad_transport_substep": (None, [P(_Box), _D, _D, P(_Rad), ctypes.c_double, P(_Stats)]),
-        "oracle_exchange_cell": (ctypes.c_int, [P(_Rad), ctypes.c_double, _D, _D, P(ctypes.c_int)]),
+        "oracle_exchange_cell": (ctypes.c_int, [P(_Rad), ctypes.c_double, ctypes.c_double, _D, _D, P(ctypes.c_int)]),
         "oracle_exchange_all": (None, [P(_Box), _D, _D, P(_Rad), ctypes.c_double, P(_Stats)]),
-        "oracle_exchange_series": (ctypes.c_double, [P(_Rad), ctypes.c_double, ctypes.c_int64, _D, _D, _D,
-                                                     ctypes.c_int64]),
+        "oracle_exchange_series": (ctypes.c_double, [P(_Rad), ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                                     _D, _D, _D, ctypes.c_int64]),
         "oracle_rhd_step": (None, [P(_Box), _D, _D, P(_Rad), ctypes.c_double, P(_Stats)]),
         "oracle_batch_step": (None, [ctypes.c_int32, P(_Box), P(_D), P(_D), ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int, P(_Rad), P(_Stats)]),
@@ -102,6 +103,8 @@ def _rad(p):
     for k in ("newton_max_iter", "nsub_max", "closure", "tau_correction", "eos"):
         setattr(r, k, int(p[k]))
     r.recon = int(p.get("recon", 0))
+    src = p.get("source")  # per-cell source rate j, one variable in the box layout (the dict keeps it alive)
+    r.src = _ptr(src) if src is not None else ctypes.cast(None, _D)
     return r
 
 
@@ -175,12 +178,14 @@ def rad_transport_substep(b, Ur, Ug, p, dt):
     return _stats(st)
 
 
-def exchange_cell(p, dt, gas, rad):
-    """Coupling update of one cell; returns (gas, rad, converged, iterations)."""
+def exchange_cell(p, dt, gas, rad, S=0.0):
+    """Coupling update of one cell with radiation source S (energy density
+    added over dt); returns (gas, rad, converged, iterations)."""
     g = np.ascontiguousarray(gas, dtype=np.float64).copy()
     r = np.ascontiguousarray(rad, dtype=np.float64).copy()
     it = ctypes.c_int(0)
-    fail = _load().oracle_exchange_cell(ctypes.byref(_rad(p)), float(dt), _ptr(g), _ptr(r), ctypes.byref(it))
+    fail = _load().oracle_exchange_cell(ctypes.byref(_rad(p)), float(dt), float(S), _ptr(g), _ptr(r),
+                                        ctypes.byref(it))
     return g, r, fail == 0, it.value
 
 
@@ -191,12 +196,12 @@ def exchange_all(b, Ug, Ur, p, dt):
     return _stats(st)
 
 
-def exchange_series(p, dt, nsteps, gas, rad, every):
+def exchange_series(p, dt, nsteps, gas, rad, every, S=0.0):
     g = np.ascontiguousarray(gas, dtype=np.float64).copy()
     r = np.ascontiguousarray(rad, dtype=np.float64).copy()
     out = np.zeros(int(nsteps) // int(every), dtype=np.float64)
-    _load().oracle_exchange_series(ctypes.byref(_rad(p)), float(dt), int(nsteps), _ptr(g), _ptr(r), _ptr(out),
-                                   int(every))
+    _load().oracle_exchange_series(ctypes.byref(_rad(p)), float(dt), float(S), int(nsteps), _ptr(g), _ptr(r),
+                                   _ptr(out), int(every))
     return out, g, r
 
 

@@ -640,13 +640,12 @@ void oracle_rad_transport_substep(const ob_box* b, double* Ur, const double* Ug,
 /* gas = (rho, mx, my, mz, E), rad = (E_r, Fx, Fy, Fz).  Returns 0 on        */
 /* convergence, 1 if the iteration cap was reached.                          */
 /* ------------------------------------------------------------------------ */
-int oracle_exchange_cell(const ob_rad* p, double dt, double* gas, double* rad, int* iters) {
+int oracle_exchange_cell(const ob_rad* p, double dt, double Ssrc, double* gas, double* rad, int* iters) {
   const double rho = gas[0];
   const double c = p->c, ch = p->chat;
   const double Ek0 = 0.5 * ((gas[1] * gas[1] + gas[2] * gas[2]) + gas[3] * gas[3]) / rho;
   const double Eg0 = gas[4] - Ek0;
   const double Er0 = rad[0];
-  const double Ssrc = 0.0;
   const double Etot = Eg0 + (c / ch) * (Er0 + Ssrc);
   double Eg = Eg0, Er = Er0;
   int it, ok = 0;
@@ -715,7 +714,8 @@ void oracle_exchange_all(const ob_box* b, double* Ug, double* Ur, const ob_rad* 
         for (int v = 0; v < 5; ++v) gas[v] = Ug[v * g.vs + o];
         for (int v = 0; v < 4; ++v) rad[v] = Ur[v * g.vs + o];
         int it = 0;
-        fails += oracle_exchange_cell(p, dt, gas, rad, &it);
+        const double S = p->src ? dt * p->src[o] : 0.0;
+        fails += oracle_exchange_cell(p, dt, S, gas, rad, &it);
         if (it > itmax) itmax = it;
         for (int v = 0; v < 5; ++v) Ug[v * g.vs + o] = gas[v];
         for (int v = 0; v < 4; ++v) Ur[v * g.vs + o] = rad[v];
@@ -729,12 +729,12 @@ void oracle_exchange_all(const ob_box* b, double* Ug, double* Ur, const ob_rad* 
 /* Repeated exchange on one cell with no transport (the energy-exchange test
  * of Section 3.2).  Writes a_r-free T^4 every `every` steps into T4_out (if
  * given) and returns the final T^4. */
-double oracle_exchange_series(const ob_rad* p, double dt, int64_t nsteps, double* gas, double* rad, double* T4_out,
-                              int64_t every) {
+double oracle_exchange_series(const ob_rad* p, double dt, double S, int64_t nsteps, double* gas, double* rad,
+                              double* T4_out, int64_t every) {
   double T4 = 0.0;
   for (int64_t s = 0; s < nsteps; ++s) {
     int it;
-    oracle_exchange_cell(p, dt, gas, rad, &it);
+    oracle_exchange_cell(p, dt, S, gas, rad, &it);
     const double Eg = gas[4] - 0.5 * ((gas[1] * gas[1] + gas[2] * gas[2]) + gas[3] * gas[3]) / gas[0];
     if (p->eos == 1) {
       T4 = 4.0 * Eg / p->alpha_cv;
@@ -790,7 +790,10 @@ void oracle_rhd_step(const ob_box* b, double* Ug, double* Ur, const ob_rad* p, d
  * count from chat, every box advanced with them.  Ur[i] == NULL marks a
  * hydro-only box. */
 void oracle_batch_step(int32_t nbox, const ob_box* boxes, double* const* Ug, double* const* Ur, double gamma_h,
-                       double cfl, int recon_h, const ob_rad* p, ob_stats* st) {
+                       double cfl, int recon_h, const ob_rad* p_in, ob_stats* st) {
+  ob_rad q = *p_in;  /* a level step takes no per-cell source */
+  q.src = NULL;
+  const ob_rad* p = &q;
   double dt_h = INFINITY, dxm = INFINITY;
   int any_rad = 0;
   for (int i = 0; i < nbox; ++i) {

@@ -33,6 +33,8 @@ typedef struct {
 typedef struct {
   double c, chat, a_r, kappa_P, kappa_R, gamma, alpha_cv, cfl, newton_tol;
   int32_t newton_max_iter, nsub_max, closure, tau_correction, eos, recon;
+  const double* src;  /* NULL, or the radiation energy source rate j per cell (one variable
+                         in the box layout); the coupling adds S = dt j (Section 2.2.3) */
 } ob_rad;   /* closure: 0 Levermore, 1 Eddington.  eos: 0 ideal (P = rho T),
                1 E_g = alpha T^4 / 4.  recon: 0 PPM, 1 PLM (hydro and radiation). */
 
@@ -52,10 +54,11 @@ void   oracle_hydro_step(const ob_box* b, double* U, double gamma, double cfl, d
                          ob_stats* st);
 void   oracle_rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const ob_rad* p, double* L, ob_stats* st);
 void   oracle_rad_transport_substep(const ob_box* b, double* Ur, const double* Ug, const ob_rad* p, double dt, ob_stats* st);
-int    oracle_exchange_cell(const ob_rad* p, double dt, double* rho_m_E /*5*/, double* Er_F /*4*/, int* iters);
+int    oracle_exchange_cell(const ob_rad* p, double dt, double S, double* rho_m_E /*5*/, double* Er_F /*4*/,
+                            int* iters);
 void   oracle_exchange_all(const ob_box* b, double* Ug, double* Ur, const ob_rad* p, double dt, ob_stats* st);
-double oracle_exchange_series(const ob_rad* p, double dt, int64_t nsteps, double* gas /*5*/, double* rad /*4*/,
-                              double* T4_out, int64_t every);
+double oracle_exchange_series(const ob_rad* p, double dt, double S, int64_t nsteps, double* gas /*5*/,
+                              double* rad /*4*/, double* T4_out, int64_t every);
 void   oracle_rhd_step(const ob_box* b, double* Ug, double* Ur, const ob_rad* p, double dt_in, ob_stats* st);
 void   oracle_batch_step(int32_t nbox, const ob_box* boxes, double* const* Ug, double* const* Ur,
                          double gamma_h, double cfl, int recon_h, const ob_rad* p, ob_stats* st);

@@ -37,7 +37,8 @@ class QkRadParams(ctypes.Structure):
                 ("kappa_P", ctypes.c_double), ("kappa_R", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("alpha_cv", ctypes.c_double), ("cfl", ctypes.c_double), ("newton_tol", ctypes.c_double),
                 ("newton_max_iter", ctypes.c_int32), ("nsub_max", ctypes.c_int32), ("closure", ctypes.c_int32),
-                ("tau_correction", ctypes.c_int32), ("eos", ctypes.c_int32), ("reconstruction", ctypes.c_int32)]
+                ("tau_correction", ctypes.c_int32), ("eos", ctypes.c_int32), ("reconstruction", ctypes.c_int32),
+                ("source", ctypes.c_void_p)]
 
 
 class QuokkaError(RuntimeError):
@@ -109,13 +110,17 @@ def hydro_params(gamma, cfl, recon=0):
     return QkHydroParams(float(gamma), float(cfl), int(recon))
 
 
-def rad_params(p):
+def rad_params(p, source=None):
+    """Radiation parameters from a dict; `source` is None or a device tensor of
+    the per-cell radiation source rate (box shape, state dtype), which the
+    caller keeps alive while the library uses it."""
     r = QkRadParams()
     for k in ("c", "chat", "a_r", "kappa_P", "kappa_R", "gamma", "alpha_cv", "cfl", "newton_tol"):
         setattr(r, k, float(p[k]))
     for k in ("newton_max_iter", "nsub_max", "closure", "tau_correction", "eos"):
         setattr(r, k, int(p[k]))
     r.reconstruction = int(p.get("recon", 0))
+    r.source = None if source is None else source.data_ptr()
     return r
 
 

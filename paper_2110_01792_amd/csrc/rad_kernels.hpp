@@ -18,6 +18,7 @@ namespace qk {
 struct RadParamsDev {
   double c, chat, a_r, kappa_P, kappa_R, gamma, alpha_cv, newton_tol;
   int newton_max_iter, closure, tau_correction, eos, recon;
+  const void* src;  // NULL or per-cell radiation source rate j (state precision)
 };
 
 template <class S, class R>
@@ -90,16 +91,18 @@ __device__ __forceinline__ void rad_face(const R* sl, const R* sr, const R* cl, 
 }
 
 // Matter-radiation coupling of one cell (Section 2.2.3), FP64 throughout.
-// gas = (rho, mx, my, mz, E), rad = (E_r, Fx, Fy, Fz); returns iterations used,
-// sets *fail when the iteration cap is reached.
-__device__ __forceinline__ int exchange(const RadParamsDev& p, double dt, double* gas, double* rad, bool& fail) {
+// gas = (rho, mx, my, mz, E), rad = (E_r, Fx, Fy, Fz); S is the optional
+// radiation source added over dt; returns iterations used, sets *fail when the
+// iteration cap is reached.
+__device__ __forceinline__ int exchange(const RadParamsDev& p, double dt, double S, double* gas, double* rad,
+                                        bool& fail) {
   const double rho = gas[0];
   const double c = p.c, ch = p.chat;
   const double coc = c / ch;
   const double Ek0 = 0.5 * ((gas[1] * gas[1] + gas[2] * gas[2]) + gas[3] * gas[3]) / rho;
   const double Eg0 = gas[4] - Ek0;
   const double Er0 = rad[0];
-  const double Etot = Eg0 + coc * Er0;
+  const double Etot = Eg0 + coc * (Er0 + S);
   const double inv_Etot = 1.0 / Etot;
   const double k1 = dt * rho * p.kappa_P * ch;         // dR/d(a_r T^4 - E_r)
   const double dFG_dEr = -c * dt * rho * p.kappa_P;
@@ -122,7 +125,7 @@ __device__ __forceinline__ int exchange(const RadParamsDev& p, double dt, double
     }
     const double R = k1 * (p.a_r * T4 - Er);
     const double FG = (Eg - Eg0) + coc * R;
-    const double FR = (Er - Er0) - R;
+    const double FR = (Er - Er0) - (R + S);
     if (fabs(FG * inv_Etot) < p.newton_tol && fabs(coc * FR * inv_Etot) < p.newton_tol) {
       conv = true;
       break;
@@ -266,6 +269,7 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
   double cq[4];                 // own column, plane k+3 (prefetched)
   double hq[HPT][4];            // halo ring of plane k (prefetched)
   double uo[4], un0[4], gas[5];
+  double srate = 0.0;  // radiation source rate of own cell (stage 2)
 
   // (E, F) -> (E, f = F / (c E))
   auto to_q = [&](const double* u, R* Q, bool& flag) {
@@ -370,6 +374,7 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
         load4(a.Un, o, un0);
 #pragma unroll
         for (int v = 0; v < 5; ++v) gas[v] = double(Ug[o + v * vs]);
+        srate = p.src ? double(((const S*)p.src)[o]) : 0.0;
       }
       if (k + 1 < z1) load4(src_at(Uin, a.Ugh, b, i, j, k + 4), o + 4 * pz, cq);
     }
@@ -504,7 +509,7 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
         aRz[v] = aRn[v];
       }
       if (STAGE == 2) {
-        const int it = exchange(p, dt, gas, un, nfail);
+        const int it = exchange(p, dt, dt * srate, gas, un, nfail);
         itmax = max(itmax, (uint32_t)it);
 #pragma unroll
         for (int v = 1; v < 5; ++v) a.Ug[o + v * vs] = S(gas[v]);

@@ -192,3 +192,39 @@ def test_rhd_deterministic(ctx):
     a = gpu_rhd(ctx, b, Ug, Ur, p, 1)
     c = gpu_rhd(ctx, b, Ug, Ur, p, 1)
     assert np.array_equal(a[0], c[0]) and np.array_equal(a[1], c[1])
+
+
+def test_rhd_with_radiation_source_matches_oracle(ctx):
+    """The optional source term of Section 2.2.3 (S = dt_sub j per cell, a
+    seeded non-negative rate array in the box layout) through quokka_rhd_step
+    against the oracle's RHD step with the same rate."""
+    torch = pytest.importorskip("torch")
+    b, Ug, Ur, p = inputs.rhd_lognormal(n=24, seed=41)
+    rng = np.random.default_rng(42)
+    j = np.zeros(b.shape)
+    j[b.interior()[1:]] = rng.uniform(0.0, 200.0, size=(b.n[2], b.n[1], b.n[0]))
+    G, R = dev(Ug), dev(Ur)
+    ctx.fill_ghosts(b, G)
+    ctx.fill_ghosts(b, R)
+    J = dev(j)
+    rp = qb.rad_params(p, source=J)
+    for _ in range(2):
+        ctx.rhd_step(b, G, R, rp)
+    assert ctx.sync_status() == qb.QK_OK
+    ps = dict(p, source=j)
+    oG, oR, _ = oracle_rhd(b, Ug, Ur, ps, nsteps=2)
+    check_pair((host(G), host(R)), (oG, oR), b, "source")
+    # the source changed the result
+    nG, nR, _ = oracle_rhd(b, Ug, Ur, p, nsteps=2)
+    assert np.max(np.abs(nR[0] - oR[0])) > 1e-3 * np.max(np.abs(oR[0]))
+
+
+def test_batch_rejects_radiation_source(ctx):
+    torch = pytest.importorskip("torch")
+    boxes, Ugs, Urs, p, hp = inputs.batch_level(nbox=2, seed=43, edges=(8,))
+    G = [dev(u) for u in Ugs]
+    R = [None if u is None else dev(u) for u in Urs]
+    J = torch.zeros(boxes[0].shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(qb.QuokkaError) as e:
+        ctx.batch_step(boxes, G, R, qb.hydro_params(hp["gamma"], hp["cfl"]), qb.rad_params(p, source=J))
+    assert e.value.status == qb.QK_EINVAL

@@ -231,6 +231,94 @@ def test_coupling_conserves_rsla_energy():
         assert abs((g[4] + (c / ch) * r[0]) - a) < 3e-12 * a
 
 
+# ------------------------------------------- optional radiation source term
+def test_source_without_coupling_adds_exactly_S():
+    """Section 2.2.3's optional source S enters the radiation residual as
+    F_R = (E_r - E_r^t) - (R + S): with no coupling (kappa = 0) the update
+    is E_r + S, the gas untouched."""
+    rng = np.random.default_rng(21)
+    for _ in range(50):
+        p = rad_params(chat=rng.uniform(5, 50), kappa_P=0.0, kappa_R=0.0)
+        rho = np.exp(rng.normal())
+        m = rng.normal(size=3) * 0.1 * rho
+        gas0 = np.array([rho, *m, rho / (p["gamma"] - 1) + 0.5 * m.dot(m) / rho])
+        rad0 = np.array([rng.uniform(0.5, 2), *(rng.normal(size=3) * 10)])
+        S = rng.uniform(0.0, 3.0)
+        g, r, ok, it = oracle.exchange_cell(p, 1e-3, gas0, rad0, S=S)
+        assert ok
+        assert r[0] == rad0[0] + S
+        assert np.array_equal(g, gas0) and np.array_equal(r[1:], rad0[1:])
+
+
+def test_source_energy_budget():
+    """With coupling, the source is the only change of E + (c/chat) E_r: the
+    residual pair gives (E_g - E_g^t) + (c/chat)(E_r - E_r^t) = (c/chat) S, and
+    the work term moves energy between E and E_r at that same weight."""
+    rng = np.random.default_rng(22)
+    for _ in range(100):
+        p = rad_params(chat=rng.uniform(5, 50), newton_tol=1e-13)
+        rho, dt = np.exp(rng.normal()), rng.uniform(1e-5, 1e-3)
+        m = rng.normal(size=3) * rho
+        gas0 = np.array([rho, *m, rho * rng.uniform(0.5, 2) / (p["gamma"] - 1) + 0.5 * m.dot(m) / rho])
+        rad0 = np.array([rng.uniform(0.5, 2) ** 4, *(rng.normal(size=3) * 50)])
+        S = rng.uniform(0.0, 0.5) * rad0[0]
+        g, r, ok, it = oracle.exchange_cell(p, dt, gas0, rad0, S=S)
+        c, ch = p["c"], p["chat"]
+        before = gas0[4] + (c / ch) * rad0[0]
+        assert ok
+        assert abs((g[4] + (c / ch) * r[0]) - (before + (c / ch) * S)) < 3e-12 * (before + (c / ch) * S)
+
+
+def test_source_linear_case_closed_form():
+    """Linear exchange (C_v = alpha T^3, beta = 4 a_r / alpha) with a constant
+    source: D = beta E_g - E_r obeys D' = (D - S) / (1 + lambda dt), lambda =
+    rho kappa chat (1 + beta c / chat), so D^n = D* + (D^0 - D*)(1 + lambda
+    dt)^-n with D* = -S / (lambda dt); E_g + (c/chat) E_r grows by (c/chat) S
+    per step."""
+    rng = np.random.default_rng(23)
+    for _ in range(20):
+        c, chat, a_r = 1000.0, rng.uniform(10, 1000), rng.uniform(0.5, 2)
+        alpha = rng.uniform(1, 8) * a_r
+        p = rad_params(chat=chat, c=c, a_r=a_r, alpha_cv=alpha, eos=1, kappa_P=rng.uniform(0.1, 5),
+                       newton_tol=1e-13)
+        rho, dt = rng.uniform(0.1, 3), rng.uniform(1e-5, 1e-2)
+        Eg, Er = rng.uniform(0.1, 10), rng.uniform(0.1, 10)
+        S = rng.uniform(0.0, 0.1) * Er
+        n = 25
+        T4, g, r = oracle.exchange_series(p, dt, n, [rho, 0, 0, 0, Eg], [Er, 0, 0, 0], n, S=S)
+        beta = 4 * a_r / alpha
+        lam_dt = rho * p["kappa_P"] * chat * (1 + beta * c / chat) * dt
+        Dstar = -S / lam_dt
+        D0 = beta * Eg - Er
+        Dn = Dstar + (D0 - Dstar) / (1 + lam_dt) ** n
+        scale = abs(Eg) + abs(Er) + n * S
+        assert abs((beta * g[4] - r[0]) - Dn) <= 1e-11 * scale
+        assert abs((g[4] + (c / chat) * r[0]) - (Eg + (c / chat) * (Er + n * S))) <= 1e-11 * (
+            Eg + (c / chat) * (Er + n * S))
+
+
+def test_source_array_in_rhd_step():
+    """A per-cell rate j in the box layout gives S = dt_sub j in every
+    coupling update of an RHD step: with the rate zero except in one cell,
+    only that cell's E + (c/chat) E_r budget changes by N (c/chat) dt_sub j
+    beyond transport."""
+    b = inputs.make_box((8, 1, 1), ng=4, bc=0)
+    p = rad_params(chat=30.0, kappa_P=0.0, kappa_R=0.0)
+    Ug = np.zeros((5,) + b.shape)
+    Ug[0] = 1.0
+    Ug[4] = 1.0 / (p["gamma"] - 1)
+    Ur = np.zeros((4,) + b.shape)
+    Ur[0] = 1.0
+    src = np.zeros(b.shape)
+    src[4, 4, 4 + 3] = 2.5
+    st0 = (Ur[0][b.interior()[1:]].sum())
+    ps = dict(p, source=src)
+    st = oracle.rhd_step(b, Ug, Ur, ps, dt=1e-3)
+    added = Ur[0][b.interior()[1:]].sum() - st0
+    assert st["nsub"] >= 1
+    assert abs(added - 2.5 * 1e-3) <= 1e-13
+
+
 # ----------------------------------------------------------- RHD step pins
 def test_substep_count_is_ten_for_rhd_workload():
     """Section 2.2.4: N_sub is capped at 10; with chat = 10 max c_s and v = 0 the
