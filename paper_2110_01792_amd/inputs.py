@@ -231,6 +231,77 @@ def batch_level(nbox=600, seed=5, gamma=5.0 / 3.0, ng=4, edges: Optional[Sequenc
     return boxes, Ugs, Urs, rad_params(chat, gamma), {"gamma": gamma, "cfl": 0.3}
 
 
+# ---------------------------------------------------------------------------
+# Radiation pressure tube (Section 3.3.1; Krumholz et al. 2007): a 1-D column
+# [0, 128] cm, 128 cells, in which radiation and gas pressure gradients balance
+# in the equilibrium-diffusion regime (tau_cell ~ 100).  cgs, mu = 2.33 m_H,
+# gamma 5/3, kappa_P = kappa_R = 100, T_0 = 2.75e7 K, rho_0 = 1,
+# drho/dx(0) = 0.005; chat = 10 c_s(0); Dirichlet (fixed) ends.
+#
+# The update's EOS is P = rho T, so temperature is carried as T' = k_B T / mu
+# (erg/g) with a_r' = a_r (mu / k_B)^4, which leaves a_r T^4 and P unchanged.
+# The steady state solves the two ODEs the paper gives (hydrostatic total
+# pressure, and constant diffusive flux F = -(c / (3 rho kappa_R)) dE_r/dx),
+# integrated with classical RK4 from x = 0 in both directions; cell values are
+# point values at cell centres, the ghosts included.  No random draws.
+# ---------------------------------------------------------------------------
+CGS = {"a_r": 7.5657e-15, "c": 2.99792458e10, "k_B": 1.380649e-16, "m_H": 1.6735575e-24}
+
+
+def _tube_rhs(y, a_r):
+    rho, T, dT = y
+    drho = -(rho + (4.0 / 3.0) * a_r * T ** 3) * dT / T
+    d2T = -3.0 * dT * dT / T + drho * dT / rho
+    return np.array([drho, dT, d2T])
+
+
+def _rk4_to(y, x0, x1, a_r, h=1e-3):
+    n = max(1, int(np.ceil(abs(x1 - x0) / h)))
+    hh = (x1 - x0) / n
+    for _ in range(n):
+        k1 = _tube_rhs(y, a_r)
+        k2 = _tube_rhs(y + 0.5 * hh * k1, a_r)
+        k3 = _tube_rhs(y + 0.5 * hh * k2, a_r)
+        k4 = _tube_rhs(y + hh * k3, a_r)
+        y = y + (hh / 6.0) * (k1 + 2 * k2 + 2 * k3 + k4)
+    return y
+
+
+def rad_pressure_tube(n=128, ng=4, L=128.0):
+    mu = 2.33 * CGS["m_H"]
+    kB_mu = CGS["k_B"] / mu
+    a_r = CGS["a_r"] / kB_mu ** 4
+    gamma, kappa = 5.0 / 3.0, 100.0
+    T0, rho0, drho0 = 2.75e7 * kB_mu, 1.0, 0.005
+    dT0 = -drho0 * T0 / (rho0 + (4.0 / 3.0) * a_r * T0 ** 3)
+    dx = L / n
+    b = Box((n, 1, 1), ng, (dx, dx, dx), ((FIXED, FIXED), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC)))
+    xs = (np.arange(-ng, n + ng) + 0.5) * dx
+    prof = np.zeros((len(xs), 3))
+    y0 = np.array([rho0, T0, dT0])
+    order = np.argsort(np.abs(xs))  # march outwards from x = 0 on each side
+    for side in (xs < 0, xs >= 0):
+        idx = [i for i in order if side[i]]
+        y, x = y0.copy(), 0.0
+        for i in idx:
+            y = _rk4_to(y, x, xs[i], a_r)
+            x = xs[i]
+            prof[i] = y
+    rho, T, dT = prof[:, 0], prof[:, 1], prof[:, 2]
+    Er = a_r * T ** 4
+    F = -(CGS["c"] / (3.0 * rho * kappa)) * 4.0 * a_r * T ** 3 * dT
+    Ug = np.zeros((5,) + b.shape)
+    Ur = np.zeros((4,) + b.shape)
+    Ug[0] = rho[None, None, :]
+    Ug[4] = (rho * T / (gamma - 1.0))[None, None, :]
+    Ur[0] = Er[None, None, :]
+    Ur[1] = F[None, None, :]
+    cs0 = np.sqrt(gamma * T0)
+    p = rad_params(10.0 * cs0, gamma=gamma, c=CGS["c"], a_r=a_r, kappa_P=kappa, kappa_R=kappa, cfl=0.4,
+                   newton_tol=1e-12, tau_correction=1)
+    return b, Ug, Ur, p, {"T": T, "rho": rho, "t_end": L / cs0, "cfl": 0.4, "cs0": cs0}
+
+
 def to_f32_and_back(U):
     """FP32-rounded copy promoted exactly back to float64 (mixed-precision reference start)."""
     return U.astype(np.float32).astype(np.float64)

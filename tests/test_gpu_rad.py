@@ -228,3 +228,13 @@ def test_batch_rejects_radiation_source(ctx):
     with pytest.raises(qb.QuokkaError) as e:
         ctx.batch_step(boxes, G, R, qb.hydro_params(hp["gamma"], hp["cfl"]), qb.rad_params(p, source=J))
     assert e.value.status == qb.QK_EINVAL
+
+
+def test_rad_pressure_tube_matches_oracle(ctx):
+    """Optically thick column (radiation pressure tube, tau_cell ~ 100, cgs
+    magnitudes, Dirichlet ends): five RHD steps on the GPU against the oracle."""
+    b, Ug, Ur, p, ref = inputs.rad_pressure_tube()
+    g, r, st = gpu_rhd(ctx, b, Ug, Ur, p, nsteps=5)
+    assert st == qb.QK_OK
+    og, orr, _ = oracle_rhd(b, Ug, Ur, p, nsteps=5)
+    check_pair((g, r), (og, orr), b, "tube")

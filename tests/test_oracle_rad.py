@@ -348,3 +348,47 @@ def test_rhd_step_invariants():
     e1 = (Ug[I][4] + (c / ch) * Ur[I][0]).sum()
     assert abs(e1 - e0) < 1e-11 * e0
     assert st["neg_cells"] == 0 and st["newton_fail"] == 0
+
+
+# ------------------------------------------------ optically thick regime
+def _tube_run(tau_correction=1, frac=1.0):
+    b, Ug, Ur, p, ref = inputs.rad_pressure_tube()
+    p = dict(p, tau_correction=tau_correction)
+    G, R = Ug.copy(), Ur.copy()
+    t, tend = 0.0, ref["t_end"] * frac
+    while t < tend * (1 - 1e-12):
+        sig = oracle.hydro_max_signal(b, G, p["gamma"])
+        dt = min(p["cfl"] * b.dx[0] / sig, tend - t)
+        st = oracle.rhd_step(b, G, R, p, dt=dt)
+        assert st["newton_fail"] == 0 and st["neg_cells"] == 0
+        t += st["dt"]
+    n, g = b.n[0], b.ng
+    rho = G[0, g, g, g:g + n]
+    Tg = (G[4, g, g, g:g + n] - 0.5 * G[1, g, g, g:g + n] ** 2 / rho) * (p["gamma"] - 1) / rho
+    Tr = (R[0, g, g, g:g + n] / p["a_r"]) ** 0.25
+    return Tg / ref["T"][g:g + n] - 1, Tr / ref["T"][g:g + n] - 1, b, p
+
+
+def test_rad_pressure_tube_holds_diffusion_steady_state():
+    """Section 3.3.1 (radiation pressure tube, tau_cell ~ 100): the steady
+    state built from the paper's two ODEs stays put for a sound-crossing time
+    at CFL 0.4 on 128 cells, gas and radiation temperatures equal.  The paper
+    reports agreement to better than 0.2 %; with every variable held at its
+    Dirichlet value in the ghost cells the split stiff flux source leaves a
+    boundary layer, so the 0.2 % bar is checked on the interior three quarters
+    and the whole column to 2 %."""
+    dTg, dTr, b, p = _tube_run()
+    n = b.n[0]
+    assert p["chat"] == pytest.approx(4.03e8, rel=2e-3)  # chat = 10 c_s,0 as stated
+    k = n // 8
+    assert np.max(np.abs(dTg[k:-k])) < 2e-3
+    assert np.max(np.abs(dTg)) < 2e-2
+    assert np.max(np.abs(dTg - dTr)) < 1e-5  # tight coupling: T_rad = T_gas
+
+
+def test_rad_pressure_tube_exercises_optical_depth_factor():
+    """The optical-depth factor (min(1, 1/tau) on the HLL dissipation) is active
+    in the tube (tau_cell ~ 100) and changes the solution."""
+    a, _, _, _ = _tube_run(tau_correction=1, frac=0.05)
+    c, _, _, _ = _tube_run(tau_correction=0, frac=0.05)
+    assert np.max(np.abs(a - c)) > 1e-5
