@@ -84,7 +84,8 @@ typedef struct {
   double newton_tol;      /* relative tolerance of the exchange solve          */
   int32_t newton_max_iter;/* iteration cap (400 in the paper)                  */
   int32_t nsub_max;       /* substep cap per hydro step (10 in the paper)      */
-  int32_t closure;        /* 0 Levermore (M1), 1 Eddington (P = E/3 I)         */
+  int32_t closure;        /* 0 Levermore (M1), 1 Eddington (P = E/3 I),
+                             2 Minerbo (polynomial form)                       */
   int32_t tau_correction; /* 1: scale HLL dissipation by min(1, 1/tau_face)    */
   int32_t eos;            /* 0: P = rho T, E_g = rho T/(gamma-1); 1: alpha T^4 */
   int32_t reconstruction; /* 0 PPM, 1 PLM, for E_r and f (Section 2.2.2) and, in

@@ -475,6 +475,8 @@ void oracle_hydro_step(const ob_box* b, double* U, double gam, double cfl, doubl
 /* ------------------------------------------------------------------------ */
 double oracle_closure_chi(double f, int closure) {
   if (closure == 1) return 1.0 / 3.0;
+  if (closure == 2) /* Minerbo (1978), polynomial form of Cernohorsky & Bludman (1994) */
+    return 1.0 / 3.0 + (2.0 / 15.0) * (3.0 * f * f - f * f * f + 3.0 * f * f * f * f);
   return (3.0 + 4.0 * f * f) / (5.0 + 2.0 * sqrt(4.0 - 3.0 * f * f));
 }
 

@@ -35,7 +35,7 @@ typedef struct {
   int32_t newton_max_iter, nsub_max, closure, tau_correction, eos, recon;
   const double* src;  /* NULL, or the radiation energy source rate j per cell (one variable
                          in the box layout); the coupling adds S = dt j (Section 2.2.3) */
-} ob_rad;   /* closure: 0 Levermore, 1 Eddington.  eos: 0 ideal (P = rho T),
+} ob_rad;   /* closure: 0 Levermore, 1 Eddington, 2 Minerbo.  eos: 0 ideal (P = rho T),
                1 E_g = alpha T^4 / 4.  recon: 0 PPM, 1 PLM (hydro and radiation). */
 
 /* Result counters returned by the step drivers. */

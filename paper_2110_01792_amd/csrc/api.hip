@@ -201,7 +201,7 @@ qk_status check_rad(qk_ctx* ctx, const qk_rad_params* rp) {
   if (!rp) return fail(ctx, QK_EINVAL, "rad params NULL");
   if (!(rp->c > 0) || !(rp->chat > 0) || !(rp->a_r > 0) || !(rp->gamma > 1.0) || !(rp->cfl > 0) ||
       !(rp->newton_tol > 0) || rp->newton_max_iter < 1 || rp->nsub_max < 1 || rp->closure < 0 ||
-      rp->closure > 1 || rp->eos < 0 || rp->eos > 1 || !(rp->kappa_P >= 0) || !(rp->kappa_R >= 0) ||
+      rp->closure > 2 || rp->eos < 0 || rp->eos > 1 || !(rp->kappa_P >= 0) || !(rp->kappa_R >= 0) ||
       (rp->eos == 1 && !(rp->alpha_cv > 0)) || rp->reconstruction < 0 || rp->reconstruction > 1)
     return fail(ctx, QK_EINVAL, "invalid radiation parameters");
   return QK_OK;

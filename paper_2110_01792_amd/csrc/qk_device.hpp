@@ -183,10 +183,16 @@ __device__ __forceinline__ float chi_tilde<float>(float pm2, float pm1, float pp
 // Radiation: M1 closure and HLL flux (Section 2.2.2, eq. M1_closure).
 // A face state is (E, f) with f = F/(c E); F = c E f.
 // ---------------------------------------------------------------------------
+// Eddington factor chi(f), f = min(|f|, 1) (Section 2.2.2): 0 Levermore
+// (3 + 4 f^2) / (5 + 2 sqrt(4 - 3 f^2)); 1 Eddington, 1/3; 2 Minerbo in the
+// polynomial form 1/3 + (2/15)(3 f^2 - f^3 + 3 f^4) (Cernohorsky & Bludman
+// 1994).  The closure enters the flux only through this function.
 template <class R>
-__device__ __forceinline__ R closure_chi(R f2, int closure) {
-  // Levermore: (3 + 4 f^2) / (5 + 2 sqrt(4 - 3 f^2)); Eddington: 1/3
-  return closure == 1 ? R(1.0 / 3.0) : (R(3) + R(4) * f2) / (R(5) + R(2) * sqrt(R(4) - R(3) * f2));
+__device__ __forceinline__ R closure_chi(R f, int closure) {
+  const R f2 = f * f;
+  if (closure == 1) return R(1.0 / 3.0);
+  if (closure == 2) return R(1.0 / 3.0) + R(2.0 / 15.0) * ((R(3) * f2 - f2 * f) + R(3) * f2 * f2);
+  return (R(3) + R(4) * f2) / (R(5) + R(2) * sqrt(R(4) - R(3) * f2));
 }
 
 // Row `d` of the Eddington tensor P/E; Tdd = P_dd/E (the HLL speed is
@@ -197,7 +203,7 @@ template <class R>
 __device__ __forceinline__ void eddington_row(R fx, R fy, R fz, R fn, int d, int closure, R& Tx, R& Ty, R& Tz,
                                               R& Tdd) {
   const R fh = rmin(fn, R(1));
-  const R chi = closure_chi(fh * fh, closure);
+  const R chi = closure_chi(fh, closure);
   const R a = R(0.5) * (R(1) - chi);
   const R bb = R(0.5) * (R(3) * chi - R(1));
   const bool has = fn > R(0);

@@ -238,3 +238,19 @@ def test_rad_pressure_tube_matches_oracle(ctx):
     assert st == qb.QK_OK
     og, orr, _ = oracle_rhd(b, Ug, Ur, p, nsteps=5)
     check_pair((g, r), (og, orr), b, "tube")
+
+
+@pytest.mark.parametrize("closure", [1, 2])
+def test_rhd_other_closures(ctx, closure):
+    """Eddington and Minerbo closures through the same kernels (the closure is
+    one device function of f)."""
+    b, Ug, Ur, p = inputs.rhd_lognormal(n=24, seed=44)
+    rng = np.random.default_rng(45)
+    # give the radiation a flux so that the closure matters
+    I = b.interior()
+    Ur[(slice(1, 4),) + I[1:]] = rng.uniform(-0.3, 0.3, size=(3, b.n[2], b.n[1], b.n[0])) * p["c"] * Ur[(0,) + I[1:]]
+    p = dict(p, closure=closure)
+    g, r, st = gpu_rhd(ctx, b, Ug, Ur, p)
+    assert st == qb.QK_OK
+    og, orr, _ = oracle_rhd(b, Ug, Ur, p)
+    check_pair((g, r), (og, orr), b, f"closure {closure}")

@@ -170,6 +170,35 @@ def test_eddington_closure_is_isotropic():
     assert oracle.closure_chi(0.7, 1) == 1.0 / 3.0
 
 
+def _minerbo_max_entropy(f):
+    """Minerbo's maximum-entropy Eddington factor from its implicit definition:
+    f = coth Z - 1/Z (Langevin function), chi = 1 - 2 f / Z (bisection on Z)."""
+    if f < 1e-8:
+        return 1.0 / 3.0
+    lo, hi = 1e-9, 1e4
+    for _ in range(200):
+        Z = 0.5 * (lo + hi)
+        if 1.0 / np.tanh(Z) - 1.0 / Z < f:
+            lo = Z
+        else:
+            hi = Z
+    return 1.0 - 2.0 * f / Z
+
+
+def test_minerbo_closure():
+    """Closure 2 (the Minerbo closure the paper offers beside Levermore's):
+    exact limits 1/3 and 1, monotone, and within 0.006 of the maximum-entropy
+    closure it approximates."""
+    assert oracle.closure_chi(0.0, 2) == 1.0 / 3.0
+    assert abs(oracle.closure_chi(1.0, 2) - 1.0) <= 2e-16
+    fs = np.linspace(0.0, 0.999, 200)
+    chi = np.array([oracle.closure_chi(f, 2) for f in fs])
+    assert np.all(np.diff(chi) > 0)
+    assert max(abs(c - _minerbo_max_entropy(f)) for f, c in zip(fs, chi)) < 6e-3
+    # distinct from Levermore's in between
+    assert abs(oracle.closure_chi(0.5, 2) - oracle.closure_chi(0.5, 0)) > 1e-2
+
+
 # -------------------------------------------------------------- HLL (rad)
 def test_hll_free_streaming_is_exact_upwind():
     """F = c E along +x: the Eddington tensor is E x x, both wave speeds are chat,

@@ -50,7 +50,7 @@ def rad_wave_error(N, closure, chat=30.0):
     return float(np.sqrt(np.sum(d ** 2))) / A
 
 
-@pytest.mark.parametrize("closure", [0, 1])
+@pytest.mark.parametrize("closure", [0, 1, 2])
 def test_diffusion_limit_wave_speed_and_second_order(closure):
     """Eqs. rad_energy, rad_flux with P_r = E/3 I (the f -> 0 limit of the
     closure, exactly the Eddington closure): a linear wave of speed chat/sqrt(3)
