@@ -282,7 +282,7 @@ __device__ __forceinline__ void flatten_tile(const FlatArgs<S, R>& a, int tbx, i
 
 // Single-box flattening: 16 x 14 tiles on 256 threads (each phase one item
 // per thread, as in the stage).
-constexpr int FTX = 16, FTY = 14, FNT = 256;
+constexpr int FTX = 32, FTY = 30, FNT = 1024;
 
 template <class S, class R>
 __global__ __launch_bounds__(FNT) void flatten_kernel(FlatArgs<S, R> a, int gx, int gy) {
