@@ -34,6 +34,21 @@ HYDRO_BYTES_PER_CELL_STEP = 200.0  # stage 1: read 40 + write 40; stage 2: read 
 # 13, flux differences and RK update 57.5 (mean of the stages), CFL signal of
 # stage 2 11 (mean).
 HYDRO_FLOPS_PER_CELL_STAGE = 45 * 15 + 106 * 3 + 13 + 57.5 + 11
+# HBM bytes per stage launch (mean of stages 1 and 2) from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE runs, scaled by the counts of a plain 2 GiB copy
+# (profiles/hydro_fp64_256_counters.md).  Valid only while the kernel sources
+# are the ones that were measured: reported as null once they change.
+STAGE_TRAFFIC = {"bytes_per_launch": 2.917e9, "sources_sha1": "accf1a9b15eba5b267d91e8e84a35210901e53de"}
+KERNEL_SOURCES = ("paper_2110_01792_amd/csrc/hydro_kernels.hpp", "paper_2110_01792_amd/csrc/qk_device.hpp")
+
+
+def measured_traffic():
+    import hashlib
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return STAGE_TRAFFIC["bytes_per_launch"] if h.hexdigest() == STAGE_TRAFFIC["sources_sha1"] else None
 
 
 def log(*a):
@@ -309,7 +324,8 @@ def main():
         "peak": FP64_PEAK_TFLOPS,
         "unit": "TFLOP/s",
         "frac": round(h64["stage_achieved_TFLOPs"] / FP64_PEAK_TFLOPS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(),
+        "traffic_unit": "HBM bytes per stage launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
         "kernel": "stage_kernel<double,double,1|2> (fused hydro RK stage, 16x14 tiles)",
         "flops_per_cell_launch": HYDRO_FLOPS_PER_CELL_STAGE,
         "bytes_per_cell_launch": HYDRO_BYTES_PER_CELL_STEP / 2,
