@@ -36,6 +36,10 @@ class _Rad(ctypes.Structure):
                 ("src", ctypes.POINTER(ctypes.c_double))]
 
 
+class _Region(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int32 * 3), ("hi", ctypes.c_int32 * 3)]
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("neg_cells", ctypes.c_int64), ("newton_fail", ctypes.c_int64),
                 ("newton_iter_max", ctypes.c_int64), ("nsub", ctypes.c_int32), ("dt", ctypes.c_double)]
@@ -63,6 +67,12 @@ def _load():
         "oracle_rad_transport_substep": (None, [P(_Box), _D, _D, P(_Rad), ctypes.c_double, P(_Stats)]),
         "oracle_exchange_cell": (ctypes.c_int, [P(_Rad), ctypes.c_double, ctypes.c_double, _D, _D, P(ctypes.c_int)]),
         "oracle_exchange_all": (None, [P(_Box), _D, _D, P(_Rad), ctypes.c_double, P(_Stats)]),
+        "oracle_hydro_step_reg": (None, [P(_Box), _D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_int, P(_Region), _D, ctypes.c_double, P(_Stats)]),
+        "oracle_average_down": (None, [P(_Box), _D, P(_Box), _D, P(ctypes.c_int32), ctypes.c_int]),
+        "oracle_prolong": (None, [P(_Box), _D, _D, ctypes.c_double, P(_Box), _D, P(ctypes.c_int32), ctypes.c_int,
+                                  ctypes.c_int]),
+        "oracle_reflux": (None, [P(_Box), _D, P(_Region), _D, P(_Box), _D, ctypes.c_int]),
         "oracle_exchange_series": (ctypes.c_double, [P(_Rad), ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                                      _D, _D, _D, ctypes.c_int64]),
         "oracle_rhd_step": (None, [P(_Box), _D, _D, P(_Rad), ctypes.c_double, P(_Stats)]),
@@ -267,3 +277,48 @@ def hll_rad(EL, FL, ER, FR, direction, p, eps=1.0):
     _load().oracle_hll_rad(float(EL), _ptr(a), float(ER), _ptr(b), int(direction), ctypes.byref(_rad(p)),
                            float(eps), _ptr(out))
     return out
+
+
+# ------------------------------------------------------------ AMR (ratio 2)
+def region_size(lo, hi, nvar=5):
+    """Doubles in a flux register over region [lo, hi)."""
+    m = [hi[d] - lo[d] for d in range(3)]
+    return nvar * 2 * (m[1] * m[2] + m[0] * m[2] + m[0] * m[1])
+
+
+def _region(lo, hi):
+    r = _Region()
+    for d in range(3):
+        r.lo[d] = int(lo[d])
+        r.hi[d] = int(hi[d])
+    return r
+
+
+def _i3(v):
+    return (ctypes.c_int32 * 3)(*[int(x) for x in v])
+
+
+def hydro_step_reg(b, U, gamma, cfl, dt, lo, hi, reg, weight=1.0, recon=0):
+    """Hydro step that adds weight * dt/2 * F of both RK stages at the faces
+    bounding region [lo, hi) to the FP64 register `reg`."""
+    _check(b, U, 5)
+    assert reg.dtype == np.float64 and reg.size == region_size(lo, hi)
+    st = _Stats()
+    _load().oracle_hydro_step_reg(ctypes.byref(_box(b)), _ptr(U), float(gamma), float(cfl), float(dt), int(recon),
+                                  ctypes.byref(_region(lo, hi)), _ptr(reg), float(weight), ctypes.byref(st))
+    return _stats(st)
+
+
+def average_down(fine, Uf, coarse, Uc, off, nvar=5):
+    _load().oracle_average_down(ctypes.byref(_box(fine)), _ptr(Uf), ctypes.byref(_box(coarse)), _ptr(Uc), _i3(off),
+                                int(nvar))
+
+
+def prolong(coarse, Uc0, Uc1, alpha, fine, Uf, off, nvar=5, interior=False):
+    _load().oracle_prolong(ctypes.byref(_box(coarse)), _ptr(Uc0), _ptr(Uc1), float(alpha), ctypes.byref(_box(fine)),
+                           _ptr(Uf), _i3(off), int(nvar), int(bool(interior)))
+
+
+def reflux(coarse, Uc, lo, hi, reg_c, fine, reg_f, nvar=5):
+    _load().oracle_reflux(ctypes.byref(_box(coarse)), _ptr(Uc), ctypes.byref(_region(lo, hi)), _ptr(reg_c),
+                          ctypes.byref(_box(fine)), _ptr(reg_f), int(nvar))

@@ -264,7 +264,17 @@ static double chi_tilde(const double* P, const double* u, size_t o, ptrdiff_t s)
     for (int j = (J0); j < (J1); ++j)                               \
       for (int i = (I0); i < (I1); ++i)
 
+static void record_region(const geo* g, const double* Fd, const ob_region* r, double* reg, double w);
+
+static void hydro_rhs(const ob_box* b, const double* U, double gam, int recon, double* L, ob_stats* st,
+                      const ob_region* r, double* reg, double w);
+
 void oracle_hydro_rhs(const ob_box* b, const double* U, double gam, int recon, double* L, ob_stats* st) {
+  hydro_rhs(b, U, gam, recon, L, st, NULL, NULL, 0.0);
+}
+
+static void hydro_rhs(const ob_box* b, const double* U, double gam, int recon, double* L, ob_stats* st,
+                      const ob_region* r, double* reg, double w) {
   geo g = make_geo(b);
   const size_t vs = g.vs;
   double* W = (double*)malloc(5 * vs * sizeof(double));
@@ -382,6 +392,7 @@ void oracle_hydro_rhs(const ob_box* b, const double* U, double gam, int recon, d
       L[v * vs + o] = -((t[0] + t[1]) + t[2]);
     }
   }
+  if (reg) record_region(&g, Fd, r, reg, w);
   if (st) st->neg_cells += neg;
   free(W);
   free(cht);
@@ -389,6 +400,34 @@ void oracle_hydro_rhs(const ob_box* b, const double* U, double gam, int recon, d
   free(aL);
   free(aR);
   free(Fd);
+}
+
+/* Add w * F at every face on the boundary of region r (face c-1/2 of axis d
+ * is stored at cell c in Fd). */
+static void record_region(const geo* g, const double* Fd, const ob_region* r, double* reg, double w) {
+  const int m0 = r->hi[0] - r->lo[0], m1 = r->hi[1] - r->lo[1], m2 = r->hi[2] - r->lo[2];
+  const size_t nx = (size_t)2 * m1 * m2, ny = (size_t)2 * m0 * m2;
+  /* axes skipped as inactive (one cell, non-fixed) carry no fluxes here */
+  if (!g->act[0] || !g->act[1] || !g->act[2]) return;
+  double* rx = reg;
+  double* ry = reg + 5 * nx;
+  double* rz = reg + 5 * (nx + ny);
+  for (int v = 0; v < 5; ++v)
+    for (int side = 0; side < 2; ++side) {
+      const int fx = side ? r->hi[0] : r->lo[0], fy = side ? r->hi[1] : r->lo[1], fz = side ? r->hi[2] : r->lo[2];
+      for (int k = r->lo[2]; k < r->hi[2]; ++k)
+        for (int j = r->lo[1]; j < r->hi[1]; ++j)
+          rx[((size_t)(v * 2 + side) * m2 + (k - r->lo[2])) * m1 + (j - r->lo[1])] +=
+              w * Fd[(size_t)(0 * 5 + v) * g->vs + IX(g, fx, j, k)];
+      for (int k = r->lo[2]; k < r->hi[2]; ++k)
+        for (int i = r->lo[0]; i < r->hi[0]; ++i)
+          ry[((size_t)(v * 2 + side) * m2 + (k - r->lo[2])) * m0 + (i - r->lo[0])] +=
+              w * Fd[(size_t)(1 * 5 + v) * g->vs + IX(g, i, fy, k)];
+      for (int j = r->lo[1]; j < r->hi[1]; ++j)
+        for (int i = r->lo[0]; i < r->hi[0]; ++i)
+          rz[((size_t)(v * 2 + side) * m1 + (j - r->lo[1])) * m0 + (i - r->lo[0])] +=
+              w * Fd[(size_t)(2 * 5 + v) * g->vs + IX(g, i, j, fz)];
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -441,6 +480,24 @@ static void euler_interior(const geo* g, int nvar, const double* Un, double* U1,
   }
 }
 
+static void hydro_rk2_reg(const ob_box* b, double* U, double gam, double dt, int recon, ob_stats* st,
+                          const ob_region* r, double* reg, double w) {
+  geo g = make_geo(b);
+  const size_t nb = 5 * g.vs * sizeof(double);
+  double* U1 = (double*)malloc(nb);
+  double* Lb = (double*)calloc(5 * g.vs, sizeof(double));
+  memcpy(U1, U, nb); /* fixed ghosts of the stage state equal those of U */
+  /* U^{n+1} = U^n + dt/2 (L(U^n) + L(U^1)): each stage's fluxes enter with dt/2 */
+  hydro_rhs(b, U, gam, recon, Lb, st, r, reg, 0.5 * dt * w);
+  euler_interior(&g, 5, U, U1, Lb, dt);
+  oracle_fill_ghosts(b, U1, 5);
+  hydro_rhs(b, U1, gam, recon, Lb, st, r, reg, 0.5 * dt * w);
+  rk2_interior(&g, 5, U, U1, Lb, dt);
+  oracle_fill_ghosts(b, U, 5);
+  free(U1);
+  free(Lb);
+}
+
 static void hydro_rk2(const ob_box* b, double* U, double gam, double dt, int recon, ob_stats* st) {
   geo g = make_geo(b);
   const size_t nb = 5 * g.vs * sizeof(double);
@@ -466,6 +523,119 @@ void oracle_hydro_step(const ob_box* b, double* U, double gam, double cfl, doubl
     st->dt = dt;
     st->nsub = 0;
   }
+}
+
+void oracle_hydro_step_reg(const ob_box* b, double* U, double gam, double cfl, double dt_in, int recon,
+                           const ob_region* r, double* reg, double weight, ob_stats* st) {
+  oracle_fill_ghosts(b, U, 5);
+  double dt = dt_in;
+  if (!(dt > 0.0)) dt = cfl * dx_min(b) / oracle_hydro_max_signal(b, U, gam);
+  hydro_rk2_reg(b, U, gam, dt, recon, st, r, reg, weight);
+  if (st) {
+    st->dt = dt;
+    st->nsub = 0;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* AMR coarse-fine operations, refinement ratio 2 (Section 2.2: conservative */
+/* linear interpolation onto fine cells, conservative average-down, flux-     */
+/* register synchronisation of the coarse cells next to the fine region).     */
+/* ------------------------------------------------------------------------ */
+static inline int fdiv2(int i) { return (i >= 0) ? i / 2 : -((1 - i) / 2); } /* floor(i / 2) */
+
+void oracle_average_down(const ob_box* fine, const double* Uf, const ob_box* coarse, double* Uc,
+                         const int32_t off[3], int nvar) {
+  geo gf = make_geo(fine), gc = make_geo(coarse);
+  for (int v = 0; v < nvar; ++v)
+    for (int K = 0; K < fine->n[2] / 2; ++K)
+      for (int J = 0; J < fine->n[1] / 2; ++J)
+        for (int I = 0; I < fine->n[0] / 2; ++I) {
+          const double* f = Uf + (size_t)v * gf.vs;
+          double s = 0.0;
+          for (int c = 0; c < 8; ++c) s += f[IX(&gf, 2 * I + (c & 1), 2 * J + ((c >> 1) & 1), 2 * K + (c >> 2))];
+          Uc[(size_t)v * gc.vs + IX(&gc, off[0] + I, off[1] + J, off[2] + K)] = s / 8.0;
+        }
+}
+
+void oracle_prolong(const ob_box* coarse, const double* Uc0, const double* Uc1, double alpha, const ob_box* fine,
+                    double* Uf, const int32_t off[3], int nvar, int interior) {
+  geo gf = make_geo(fine), gc = make_geo(coarse);
+  const int ng = fine->ng;
+  for (int v = 0; v < nvar; ++v) {
+    const double* c0 = Uc0 + (size_t)v * gc.vs;
+    const double* c1 = Uc1 + (size_t)v * gc.vs;
+    for (int k = -ng; k < fine->n[2] + ng; ++k)
+      for (int j = -ng; j < fine->n[1] + ng; ++j)
+        for (int i = -ng; i < fine->n[0] + ng; ++i) {
+          const int in = i >= 0 && i < fine->n[0] && j >= 0 && j < fine->n[1] && k >= 0 && k < fine->n[2];
+          if (in && !interior) continue;
+          const int P[3] = {off[0] + fdiv2(i), off[1] + fdiv2(j), off[2] + fdiv2(k)};
+          const int f[3] = {i, j, k};
+          /* coarse value at time (1 - alpha) t0 + alpha t1 */
+          #define QC(a, b, c) ((1.0 - alpha) * c0[IX(&gc, a, b, c)] + alpha * c1[IX(&gc, a, b, c)])
+          const double q = QC(P[0], P[1], P[2]);
+          double u = q;
+          for (int d = 0; d < 3; ++d) {
+            int m[3] = {P[0], P[1], P[2]}, p[3] = {P[0], P[1], P[2]};
+            m[d] -= 1;
+            p[d] += 1;
+            const double qm = QC(m[0], m[1], m[2]), qp = QC(p[0], p[1], p[2]);
+            const double dl = q - qm, dr = qp - q, dc = qp - qm;
+            double s = 0.0;
+            if (dl * dr > 0.0) {
+              s = fmin(fmin(2.0 * fabs(dl), 2.0 * fabs(dr)), 0.5 * fabs(dc));
+              if (dc < 0.0) s = -s;
+            }
+            /* child centre at -1/4 (even fine index) or +1/4 (odd) of the coarse cell */
+            u += ((f[d] & 1) ? 0.25 : -0.25) * s;
+          }
+          #undef QC
+          Uf[(size_t)v * gf.vs + IX(&gf, i, j, k)] = u;
+        }
+  }
+}
+
+void oracle_reflux(const ob_box* coarse, double* Uc, const ob_region* r, const double* reg_c, const ob_box* fine,
+                   const double* reg_f, int nvar) {
+  geo gc = make_geo(coarse);
+  const int m0 = r->hi[0] - r->lo[0], m1 = r->hi[1] - r->lo[1], m2 = r->hi[2] - r->lo[2];
+  const int f0 = fine->n[0], f1 = fine->n[1], f2 = fine->n[2];
+  const size_t cx = (size_t)2 * m1 * m2, cy = (size_t)2 * m0 * m2;
+  const size_t fx = (size_t)2 * f1 * f2, fy = (size_t)2 * f0 * f2;
+  for (int v = 0; v < nvar; ++v)
+    for (int side = 0; side < 2; ++side) {
+      /* low face: the outside cell has it as its right face, and gains
+         (coarse - fine) / dx; high face: left face, gains (fine - coarse) / dx */
+      const double sg = side ? -1.0 : 1.0;
+      for (int K = 0; K < m2; ++K)
+        for (int J = 0; J < m1; ++J) {
+          const double c = reg_c[((size_t)(v * 2 + side) * m2 + K) * m1 + J];
+          double fs = 0.0;
+          for (int q = 0; q < 4; ++q)
+            fs += reg_f[((size_t)(v * 2 + side) * f2 + 2 * K + (q >> 1)) * f1 + 2 * J + (q & 1)];
+          const int I = side ? r->hi[0] : r->lo[0] - 1;
+          Uc[(size_t)v * gc.vs + IX(&gc, I, r->lo[1] + J, r->lo[2] + K)] += sg * (c - fs / 4.0) / coarse->dx[0];
+        }
+      for (int K = 0; K < m2; ++K)
+        for (int I = 0; I < m0; ++I) {
+          const double c = reg_c[5 * cx + ((size_t)(v * 2 + side) * m2 + K) * m0 + I];
+          double fs = 0.0;
+          for (int q = 0; q < 4; ++q)
+            fs += reg_f[5 * fx + ((size_t)(v * 2 + side) * f2 + 2 * K + (q >> 1)) * f0 + 2 * I + (q & 1)];
+          const int J = side ? r->hi[1] : r->lo[1] - 1;
+          Uc[(size_t)v * gc.vs + IX(&gc, r->lo[0] + I, J, r->lo[2] + K)] += sg * (c - fs / 4.0) / coarse->dx[1];
+        }
+      for (int J = 0; J < m1; ++J)
+        for (int I = 0; I < m0; ++I) {
+          const double c = reg_c[5 * (cx + cy) + ((size_t)(v * 2 + side) * m1 + J) * m0 + I];
+          double fs = 0.0;
+          for (int q = 0; q < 4; ++q)
+            fs += reg_f[5 * (fx + fy) + ((size_t)(v * 2 + side) * f1 + 2 * J + (q >> 1)) * f0 + 2 * I + (q & 1)];
+          const int K = side ? r->hi[2] : r->lo[2] - 1;
+          Uc[(size_t)v * gc.vs + IX(&gc, r->lo[0] + I, r->lo[1] + J, K)] += sg * (c - fs / 4.0) / coarse->dx[2];
+        }
+    }
 }
 
 /* ------------------------------------------------------------------------ */

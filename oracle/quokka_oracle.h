@@ -62,6 +62,31 @@ double oracle_exchange_series(const ob_rad* p, double dt, double S, int64_t nste
 void   oracle_rhd_step(const ob_box* b, double* Ug, double* Ur, const ob_rad* p, double dt_in, ob_stats* st);
 void   oracle_batch_step(int32_t nbox, const ob_box* boxes, double* const* Ug, double* const* Ur,
                          double gamma_h, double cfl, int recon_h, const ob_rad* p, ob_stats* st);
+/* AMR level synchronisation (Section 2.2, refinement ratio 2).  A region is a
+ * range [lo, hi) of a box's interior cells.  A flux register over a region
+ * holds, per face on the region's boundary, the time-integrated flux
+ * sum over RK stages of weight * dt/2 * F (FP64), laid out as
+ *   x faces [v][side][k - lo2][j - lo1], then y faces [v][side][k - lo2][i - lo0],
+ *   then z faces [v][side][j - lo1][i - lo0]   (side 0: face lo, 1: face hi),
+ * 5 variables: 10 (m1 m2 + m0 m2 + m0 m1) doubles for m = hi - lo. */
+typedef struct {
+  int32_t lo[3], hi[3];
+} ob_region;
+void   oracle_hydro_step_reg(const ob_box* b, double* U, double gamma, double cfl, double dt_in, int recon,
+                             const ob_region* r, double* reg, double weight, ob_stats* st);
+/* Coarse cells off + (I/2) over the fine interior get the mean of their 8 children. */
+void   oracle_average_down(const ob_box* fine, const double* Uf, const ob_box* coarse, double* Uc,
+                           const int32_t off[3], int nvar);
+/* Fine cells (ghosts only, or interior and ghosts) from the coarse state
+ * (1 - alpha) Uc0 + alpha Uc1 by MC-limited linear interpolation that keeps
+ * each coarse cell's mean; fine cell 0 lies in coarse cell off. */
+void   oracle_prolong(const ob_box* coarse, const double* Uc0, const double* Uc1, double alpha, const ob_box* fine,
+                      double* Uf, const int32_t off[3], int nvar, int interior);
+/* Coarse cells just outside region r (the fine box's footprint) get the
+ * difference between the coarse register (over r) and the area mean of the
+ * fine register (over the whole fine box) on each boundary face. */
+void   oracle_reflux(const ob_box* coarse, double* Uc, const ob_region* r, const double* reg_c, const ob_box* fine,
+                     const double* reg_f, int nvar);
 double oracle_closure_chi(double fhat, int closure);
 void   oracle_closure_pressure(double E, const double F[3], double c, int closure, double P[9]);
 void   oracle_ppm_cell(const double q[5], double out_aL_aR[2]);

@@ -305,3 +305,31 @@ def rad_pressure_tube(n=128, ng=4, L=128.0):
 def to_f32_and_back(U):
     """FP32-rounded copy promoted exactly back to float64 (mixed-precision reference start)."""
     return U.astype(np.float32).astype(np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Two AMR levels (refinement ratio 2) for the level-synchronisation tests: a
+# periodic coarse box of n^3 cells on [0,1]^3 and one fine box of m^3 fine
+# cells whose lowest cell lies in coarse cell `off` (fine ghosts are FIXED:
+# the caller fills them from the coarse level).  Both levels hold point
+# values of the same smooth seeded field at their cell centres:
+# rho = 1 + 0.2 s1, P = 1 + 0.1 s2, v_d = 0.2 s_{3+d} (s_i = sum of 4 modes),
+# gamma 5/3.  Draws: 5 mode sets.
+# ---------------------------------------------------------------------------
+def two_level(n=16, m=16, off=(4, 4, 4), seed=61, gamma=5.0 / 3.0, ng=4):
+    rng = np.random.default_rng(seed)
+    modes = [_modes(rng) for _ in range(5)]
+    cb = make_box(n, ng=ng, bc=PERIODIC)
+    dxf = cb.dx[0] / 2.0
+    fo = tuple(off[d] * cb.dx[d] for d in range(3))
+    fb = Box((m, m, m), ng, (dxf, dxf, dxf), ((FIXED, FIXED),) * 3, fo)
+
+    def fill(b):
+        z, y, x = cell_centres(b)
+        full = np.ones((b.n[2], b.n[1], b.n[0]))
+        s = [_mode_sum(k, p, z, y, x) * full for (k, p) in modes]
+        U = _alloc(b, 5)
+        U[b.interior()] = _conserved(1.0 + 0.2 * s[0], 0.2 * s[2], 0.2 * s[3], 0.2 * s[4], 1.0 + 0.1 * s[1], gamma)
+        return U
+
+    return cb, fill(cb), fb, fill(fb), tuple(off), {"gamma": gamma, "cfl": 0.3}

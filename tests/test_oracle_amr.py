@@ -1,0 +1,129 @@
+"""Pins of the oracle's AMR coarse-fine operations (refinement ratio 2,
+Section 2.2): conservative average-down, conservative linear interpolation,
+flux registers and the level-synchronisation (reflux) step (no GPU)."""
+import numpy as np
+
+import oracle
+from paper_2110_01792_amd import inputs
+from tests.amr_runs import composite_totals, coarse_totals, two_level_step
+
+
+class OracleAMR:
+    copy = staticmethod(np.copy)
+
+    @staticmethod
+    def zeros(n):
+        return np.zeros(n)
+
+    fill_ghosts = staticmethod(lambda b, U: oracle.fill_ghosts(b, U))
+    max_signal = staticmethod(lambda b, U, g: oracle.hydro_max_signal(b, U, g))
+
+    @staticmethod
+    def hydro_step_reg(b, U, gamma, cfl, dt, lo, hi, reg):
+        oracle.hydro_step_reg(b, U, gamma, cfl, dt, lo, hi, reg)
+
+    @staticmethod
+    def prolong(cb, U0, U1, alpha, fb, Uf, off, interior=False):
+        oracle.prolong(cb, U0, U1, alpha, fb, Uf, off, interior=interior)
+
+    @staticmethod
+    def average_down(fb, Uf, cb, Uc, off):
+        oracle.average_down(fb, Uf, cb, Uc, off)
+
+    @staticmethod
+    def reflux(cb, Uc, lo, hi, reg_c, fb, reg_f):
+        oracle.reflux(cb, Uc, lo, hi, reg_c, fb, reg_f)
+
+
+def test_average_down_is_the_mean_of_children():
+    cb, Uc, fb, Uf, off, p = inputs.two_level()
+    oracle.average_down(fb, Uf, cb, Uc, off)
+    g = cb.ng
+    for v in range(5):
+        fine = Uf[v][fb.interior()[1:]]
+        coarse = Uc[v, g + off[2]:g + off[2] + 8, g + off[1]:g + off[1] + 8, g + off[0]:g + off[0] + 8]
+        blocks = fine.reshape(8, 2, 8, 2, 8, 2).mean(axis=(1, 3, 5))
+        assert np.allclose(coarse, blocks, rtol=0, atol=4e-16 * np.abs(fine).max())
+        assert abs(coarse.sum() * 8 - fine.sum()) <= 1e-12 * np.abs(fine).sum()
+
+
+def test_prolongation_conserves_and_is_exact_for_linear_data():
+    cb, Uc, fb, Uf, off, p = inputs.two_level()
+    oracle.fill_ghosts(cb, Uc)
+    # conservation: the mean of the 8 children is the coarse value
+    F = np.zeros_like(Uf)
+    oracle.prolong(cb, Uc, Uc, 0.0, fb, F, off, interior=True)
+    back = Uc.copy()
+    oracle.average_down(fb, F, cb, back, off)
+    assert np.allclose(back, Uc, rtol=1e-14, atol=1e-15)
+    # linear field: children reproduce it exactly (the MC slope is the central difference)
+    z, y, x = inputs.cell_centres(cb, with_ghosts=True)
+    L = np.zeros_like(Uc)
+    L[:] = (1.0 + 0.3 * x + 0.2 * y - 0.1 * z)[None]
+    zf, yf, xf = inputs.cell_centres(fb, with_ghosts=True)
+    want = 1.0 + 0.3 * xf + 0.2 * yf - 0.1 * zf
+    F = np.zeros_like(Uf)
+    oracle.prolong(cb, L, L, 0.0, fb, F, off, interior=True)
+    assert np.max(np.abs(F[0] - want)) < 1e-14
+    # ghosts only: the interior is untouched
+    F = np.full_like(Uf, 7.0)
+    oracle.prolong(cb, L, L, 0.0, fb, F, off, interior=False)
+    assert np.all(F[fb.interior()] == 7.0)
+    g = fb.ng
+    assert np.max(np.abs(F[0, :g] - want[:g])) < 1e-14
+
+
+def test_prolongation_time_interpolation():
+    cb, Uc, fb, Uf, off, p = inputs.two_level()
+    oracle.fill_ghosts(cb, Uc)
+    U1 = Uc * 1.5
+    a = np.zeros_like(Uf)
+    b_ = np.zeros_like(Uf)
+    m = np.zeros_like(Uf)
+    oracle.prolong(cb, Uc, U1, 0.0, fb, a, off, interior=True)
+    oracle.prolong(cb, U1, Uc, 1.0, fb, b_, off, interior=True)
+    oracle.prolong(cb, Uc, U1, 0.5, fb, m, off, interior=True)
+    assert np.array_equal(a, b_)
+    assert np.allclose(m, 1.25 * a, rtol=1e-14, atol=1e-15)
+
+
+def test_flux_register_matches_change_of_the_region_total():
+    """The register over a region holds the time-integrated boundary fluxes:
+    the region's total changes by minus their outward sum."""
+    cb, Uc, fb, Uf, off, p = inputs.two_level()
+    lo, hi = (3, 5, 4), (11, 12, 9)
+    from tests.amr_runs import region_size
+    reg = np.zeros(region_size(lo, hi))
+    g = cb.ng
+    sl = (slice(None), slice(g + lo[2], g + hi[2]), slice(g + lo[1], g + hi[1]), slice(g + lo[0], g + hi[0]))
+    before = Uc[sl].reshape(5, -1).sum(axis=1)
+    oracle.hydro_step_reg(cb, Uc, p["gamma"], p["cfl"], 0.0, lo, hi, reg)
+    after = Uc[sl].reshape(5, -1).sum(axis=1)
+    m = [hi[d] - lo[d] for d in range(3)]
+    nx, ny = 2 * m[1] * m[2], 2 * m[0] * m[2]
+    rx = reg[:5 * nx].reshape(5, 2, -1).sum(axis=2)
+    ry = reg[5 * nx:5 * (nx + ny)].reshape(5, 2, -1).sum(axis=2)
+    rz = reg[5 * (nx + ny):].reshape(5, 2, -1).sum(axis=2)
+    dxc = cb.dx[0]
+    # cell-sum change = -(sum over hi faces - sum over lo faces) / dx (dx = dy = dz)
+    net = -((rx[:, 1] - rx[:, 0]) + (ry[:, 1] - ry[:, 0]) + (rz[:, 1] - rz[:, 0])) / dxc
+    assert np.allclose(after - before, net, rtol=1e-10, atol=1e-12 * np.abs(before).max())
+
+
+def test_two_level_step_conserves_only_with_reflux():
+    """Section 2.2 level synchronisation: after a coarse step, two fine steps
+    and the average-down, refluxing makes the coarse level's totals of mass,
+    momentum and energy equal the composite totals before the step (round-off);
+    without it they differ."""
+    for reflux in (True, False):
+        cb, Uc, fb, Uf, off, p = inputs.two_level()
+        oracle.average_down(fb, Uf, cb, Uc, off)
+        t0 = composite_totals(cb, Uc, fb, Uf, off)
+        for _ in range(2):
+            two_level_step(OracleAMR, cb, Uc, fb, Uf, off, p["gamma"], p["cfl"], reflux=reflux)
+        t1 = coarse_totals(cb, Uc)
+        err = np.abs(t1 - t0) / np.abs(t0).max()
+        if reflux:
+            assert np.all(err < 1e-14), err
+        else:
+            assert np.max(err) > 1e-9, err
