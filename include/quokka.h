@@ -169,6 +169,56 @@ qk_status quokka_batch_step(qk_ctx* ctx, const qk_box* boxes, int32_t nbox, void
  * named by the environment variable QK_TUNE_CACHE, if set. */
 qk_status quokka_batch_config(qk_ctx* ctx, int32_t* tile, int32_t* zc, double* tune_ms);
 
+/* ------------------------------------------------------------------------
+ * AMR level synchronisation, refinement ratio 2 (Section 2.2: conservative
+ * linear interpolation onto fine cells, conservative average-down, and the
+ * flux-register update of the coarse cells next to a fine region).
+ * A region is a range [lo, hi) of a box's interior cells (non-empty).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int32_t lo[3], hi[3];
+} qk_region;
+
+/* A flux register over a region is a caller-owned FP64 DEVICE array of
+ * 10 (m1 m2 + m0 m2 + m0 m1) doubles, m = hi - lo: x faces [v][side][k][j],
+ * then y faces [v][side][k][i], then z faces [v][side][j][i], indices relative
+ * to lo, side 0 the region's low face and 1 its high face, v the 5 gas
+ * variables.  quokka_hydro_step_reg is quokka_hydro_step (no fused next dt)
+ * that also ADDS weight * dt/2 * F of both RK stages (the step's
+ * time-integrated flux) at every face on the region's boundary; the caller
+ * zeroes the register.  Regions must lie in the box interior (QK_EINVAL). */
+qk_status quokka_hydro_step_reg(qk_ctx* ctx, const qk_box* box, void* U_gas, qk_precision prec,
+                                const qk_hydro_params* hp, const double* dt_dev, double dt_in,
+                                const qk_region* region, double* reg, double weight, void* stream);
+
+/* Coarse cells off + (I, J, K), 0 <= I < n_fine/2 (per axis), get the mean of
+ * their 8 fine children (nvar variables; same precision on both levels).
+ * Fine extents must be even and the footprint inside the coarse interior. */
+qk_status quokka_average_down(qk_ctx* ctx, const qk_box* fine, const void* U_fine, const qk_box* coarse,
+                              void* U_coarse, const int32_t off[3], int32_t nvar, qk_precision prec, void* stream);
+
+/* Fine cells from the coarse level at time (1 - alpha) t0 + alpha t1 (states
+ * U_c0 and U_c1, alpha in [0, 1]): the parent's value plus a quarter of the
+ * MC-limited slope per axis toward the child's side, which keeps every
+ * parent's mean.  Fine cell 0 lies in coarse cell off.  interior == 0 fills the
+ * fine ghost layers only (fill-patch of a fine box with FIXED ghosts); != 0
+ * fills the whole ghosted fine box (a new fine grid).  The parents and their
+ * slope neighbours must lie in the coarse ghosted array, whose ghosts the
+ * caller has filled. */
+qk_status quokka_prolong(qk_ctx* ctx, const qk_box* coarse, const void* U_c0, const void* U_c1, double alpha,
+                         const qk_box* fine, void* U_fine, const int32_t off[3], int32_t nvar, int32_t interior,
+                         qk_precision prec, void* stream);
+
+/* Level synchronisation: `region` is the fine box's footprint on the coarse
+ * level (fine extents = 2 (hi - lo)); reg_coarse is the coarse step's register
+ * over it, reg_fine the sum of the fine steps' registers over the whole fine
+ * box.  Each coarse cell just outside a boundary face gains
+ * (R_coarse - mean of the 4 fine faces) / dx through the region's low face and
+ * minus that through its high face. */
+qk_status quokka_reflux(qk_ctx* ctx, const qk_box* coarse, void* U_coarse, const qk_region* region,
+                        const double* reg_coarse, const qk_box* fine, const double* reg_fine, int32_t nvar,
+                        qk_precision prec, void* stream);
+
 /* Wait for the stream, then return and clear the first sticky device error
  * (QK_ENEGATIVE, QK_ENEWTON) or QK_OK. */
 qk_status quokka_sync_status(qk_ctx* ctx, void* stream);

@@ -18,7 +18,8 @@ STATUS_NAMES = {0: "QK_OK", 1: "QK_EINVAL", 2: "QK_ENOMEM", 3: "QK_EHIP", 4: "QK
 
 EXPORTED = ("quokka_ctx_create", "quokka_ctx_destroy", "quokka_last_error", "quokka_fill_ghosts",
             "quokka_compute_dt", "quokka_hydro_step", "quokka_rad_step", "quokka_rhd_step", "quokka_batch_step",
-            "quokka_sync_status", "quokka_newton_iter_max", "quokka_timing", "quokka_kernel_time", "quokka_batch_config")
+            "quokka_sync_status", "quokka_newton_iter_max", "quokka_timing", "quokka_kernel_time", "quokka_batch_config",
+            "quokka_hydro_step_reg", "quokka_average_down", "quokka_prolong", "quokka_reflux")
 K_HYDRO_STAGE, K_FLATTEN, K_RAD_STAGE, K_RAD_COUPLE, K_GHOST, K_BATCH = range(6)
 
 
@@ -26,6 +27,24 @@ class QkBox(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32 * 3), ("ng", ctypes.c_int32), ("pitch_y", ctypes.c_int64),
                 ("pitch_z", ctypes.c_int64), ("var_stride", ctypes.c_int64), ("dx", ctypes.c_double * 3),
                 ("bc", (ctypes.c_int32 * 2) * 3)]
+
+
+class QkRegion(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_int32 * 3), ("hi", ctypes.c_int32 * 3)]
+
+
+def make_region(lo, hi):
+    r = QkRegion()
+    for d in range(3):
+        r.lo[d] = int(lo[d])
+        r.hi[d] = int(hi[d])
+    return r
+
+
+def region_size(lo, hi, nvar=5):
+    """Doubles in a flux register over region [lo, hi)."""
+    m = [int(hi[d]) - int(lo[d]) for d in range(3)]
+    return nvar * 2 * (m[1] * m[2] + m[0] * m[2] + m[0] * m[1])
 
 
 class QkHydroParams(ctypes.Structure):
@@ -83,6 +102,11 @@ def load():
         "quokka_timing": (ctypes.c_int, [V, I32]),
         "quokka_kernel_time": (ctypes.c_int, [V, I32, P(D), P(ctypes.c_int64)]),
         "quokka_batch_config": (ctypes.c_int, [V, P(I32), P(I32), P(D)]),
+        "quokka_hydro_step_reg": (ctypes.c_int, [V, P(QkBox), V, ctypes.c_int, P(QkHydroParams), V, D, P(QkRegion), V,
+                                                 D, V]),
+        "quokka_average_down": (ctypes.c_int, [V, P(QkBox), V, P(QkBox), V, P(I32), I32, ctypes.c_int, V]),
+        "quokka_prolong": (ctypes.c_int, [V, P(QkBox), V, V, D, P(QkBox), V, P(I32), I32, I32, ctypes.c_int, V]),
+        "quokka_reflux": (ctypes.c_int, [V, P(QkBox), V, P(QkRegion), V, P(QkBox), V, I32, ctypes.c_int, V]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -199,6 +223,41 @@ class Context:
         self._ok(self.lib.quokka_hydro_step(self.h, ctypes.byref(make_box(b)), _ptr(Ug), _prec_of(Ug),
                                             ctypes.byref(hp), _ptr(dt_dev), float(dt), _ptr(dt_next_dev),
                                             _stream(stream)))
+
+    # ---------------------------------------------------- AMR (ratio 2)
+    def hydro_step_reg(self, b, Ug, hp, lo, hi, reg, dt=0.0, dt_dev=None, weight=1.0, stream=None):
+        """Hydro step adding weight * dt/2 * F of both stages at the faces
+        bounding region [lo, hi) to the FP64 device register `reg`."""
+        import torch
+        _check_state(Ug, b, 5)
+        if reg.dtype != torch.float64 or reg.numel() != region_size(lo, hi) or not reg.is_cuda:
+            raise ValueError("register must be a float64 device tensor of region_size(lo, hi) elements")
+        self._ok(self.lib.quokka_hydro_step_reg(self.h, ctypes.byref(make_box(b)), _ptr(Ug), _prec_of(Ug),
+                                                ctypes.byref(hp), _ptr(dt_dev), float(dt),
+                                                ctypes.byref(make_region(lo, hi)), _ptr(reg), float(weight),
+                                                _stream(stream)))
+
+    def average_down(self, fb, Uf, cb, Uc, off, nvar=5, stream=None):
+        _check_state(Uf, fb, nvar)
+        _check_state(Uc, cb, nvar)
+        o = (ctypes.c_int32 * 3)(*[int(x) for x in off])
+        self._ok(self.lib.quokka_average_down(self.h, ctypes.byref(make_box(fb)), _ptr(Uf),
+                                              ctypes.byref(make_box(cb)), _ptr(Uc), o, int(nvar), _prec_of(Uf),
+                                              _stream(stream)))
+
+    def prolong(self, cb, Uc0, Uc1, alpha, fb, Uf, off, nvar=5, interior=False, stream=None):
+        for t, b in ((Uc0, cb), (Uc1, cb), (Uf, fb)):
+            _check_state(t, b, nvar)
+        o = (ctypes.c_int32 * 3)(*[int(x) for x in off])
+        self._ok(self.lib.quokka_prolong(self.h, ctypes.byref(make_box(cb)), _ptr(Uc0), _ptr(Uc1), float(alpha),
+                                         ctypes.byref(make_box(fb)), _ptr(Uf), o, int(nvar), int(bool(interior)),
+                                         _prec_of(Uf), _stream(stream)))
+
+    def reflux(self, cb, Uc, lo, hi, reg_c, fb, reg_f, nvar=5, stream=None):
+        _check_state(Uc, cb, nvar)
+        self._ok(self.lib.quokka_reflux(self.h, ctypes.byref(make_box(cb)), _ptr(Uc),
+                                        ctypes.byref(make_region(lo, hi)), _ptr(reg_c), ctypes.byref(make_box(fb)),
+                                        _ptr(reg_f), int(nvar), _prec_of(Uc), _stream(stream)))
 
     def rad_step(self, b, Ug, Ur, rp, dt_dev=None, nsub_dev=None, dt=0.0, stream=None):
         _check_state(Ug, b, 5)

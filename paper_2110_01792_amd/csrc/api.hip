@@ -13,6 +13,7 @@
 #include "hydro_kernels.hpp"
 #include "rad_kernels.hpp"
 #include "batch.hpp"
+#include "amr_kernels.hpp"
 
 using namespace qk;
 
@@ -240,6 +241,14 @@ void launch_ghost_copy(const HostBox& hb, S* dst, const S* src, int nvar, hipStr
   hipLaunchKernelGGL(ghost_copy_kernel<S>, dim3(grid_for(total, 256, 8192)), dim3(256), 0, s, dst, src, d, nvar);
 }
 
+// Flux register of a stage launch: faces bounding region [lo, hi) add
+// w * dt/2 * F into reg (see reg_slot for the layout).
+struct RegRec {
+  double* reg;
+  int lo[3], hi[3];
+  double w;
+};
+
 struct Launch {
   int gx, gy, gz, zc;
 };
@@ -299,7 +308,7 @@ void launch_flatten(const HostBox& hb, const S* U, R* chi, double gamma, hipStre
 template <class S, class R, int STAGE>
 void launch_stage(const HostBox& hb, const S* Uin, const S* Un, S* Uout, const R* chi, double gamma,
                   const double* dt_ptr, double dt_val, unsigned long long* smax, uint32_t* err, int recon,
-                  hipStream_t s) {
+                  hipStream_t s, const RegRec* rec = nullptr) {
   const DevBox& d = hb.d;
   static const int res = resident_grid(stage_kernel<S, R, STAGE>, SNT);
   Launch L = plan(d.n0, d.n1, d.n2, STX, STY, res);
@@ -319,7 +328,16 @@ void launch_stage(const HostBox& hb, const S* Uin, const S* Un, S* Uout, const R
   a.smax = smax;
   a.err = err;
   a.recon = recon;
-  hipLaunchKernelGGL((stage_kernel<S, R, STAGE>), dim3(L.gx * L.gy * L.gz), dim3(SNT), 0, s, a);
+  a.reg = rec ? rec->reg : nullptr;
+  for (int q = 0; q < 3; ++q) {
+    a.rlo[q] = rec ? rec->lo[q] : 0;
+    a.rhi[q] = rec ? rec->hi[q] : 0;
+  }
+  a.rw = rec ? rec->w : 0.0;
+  if (rec)
+    hipLaunchKernelGGL((stage_kernel<S, R, STAGE, true>), dim3(L.gx * L.gy * L.gz), dim3(SNT), 0, s, a);
+  else
+    hipLaunchKernelGGL((stage_kernel<S, R, STAGE, false>), dim3(L.gx * L.gy * L.gz), dim3(SNT), 0, s, a);
 }
 
 template <class S>
@@ -345,7 +363,7 @@ const double* resolve_dt(qk_ctx* ctx, const HostBox& hb, const S* U, double gamm
 
 template <class S, class R>
 qk_status hydro_step_t(qk_ctx* ctx, const HostBox& hb, S* U, const qk_hydro_params* hp, const double* dt_dev,
-                       double dt_in, double* dt_next, hipStream_t s) {
+                       double dt_in, double* dt_next, hipStream_t s, const RegRec* rec = nullptr) {
   qk_status st;
   const size_t ne = (size_t)hb.elems;
   if ((st = ensure(ctx, ctx->stage_g, 5 * ne * sizeof(S))) != QK_OK) return st;
@@ -360,7 +378,7 @@ qk_status hydro_step_t(qk_ctx* ctx, const HostBox& hb, S* U, const qk_hydro_para
   launch_flatten<S, R>(hb, U, chi, hp->gamma, s);
   T.end(QK_K_FLATTEN, s);
   T.begin(QK_K_HYDRO_STAGE, s);
-  launch_stage<S, R, 1>(hb, U, U, U1, chi, hp->gamma, dtp, dtv, nullptr, &ctx->sc->err, hp->reconstruction, s);
+  launch_stage<S, R, 1>(hb, U, U, U1, chi, hp->gamma, dtp, dtv, nullptr, &ctx->sc->err, hp->reconstruction, s, rec);
   T.end(QK_K_HYDRO_STAGE, s);
   T.begin(QK_K_GHOST, s);
   launch_ghosts<S>(hb, U1, 5, s);
@@ -370,7 +388,7 @@ qk_status hydro_step_t(qk_ctx* ctx, const HostBox& hb, S* U, const qk_hydro_para
   T.end(QK_K_FLATTEN, s);
   T.begin(QK_K_HYDRO_STAGE, s);
   launch_stage<S, R, 2>(hb, U1, U, U, chi, hp->gamma, dtp, dtv, dt_next ? &ctx->sc->smax_b : nullptr,
-                        &ctx->sc->err, hp->reconstruction, s);
+                        &ctx->sc->err, hp->reconstruction, s, rec);
   T.end(QK_K_HYDRO_STAGE, s);
   T.begin(QK_K_GHOST, s);
   launch_ghosts<S>(hb, U, 5, s);
@@ -399,6 +417,7 @@ qk_status read_status(qk_ctx* ctx, hipStream_t s) {
 
 #include "api_rad.inc"
 #include "api_batch.inc"
+#include "api_amr.inc"
 
 // ---------------------------------------------------------------------------
 // exported entry points

@@ -92,6 +92,7 @@ __global__ __launch_bounds__(TX* TY) void batch_stage_kernel(const BatchBox<S, R
     a.smax = nullptr;
     a.err = err;
     a.recon = bb.recon;
+    a.reg = nullptr;
     stage_tile<S, R, TX, TY, TX * TY, false, STAGE>(a, w.bx, w.by, w.bz, sm, bad);
     __syncthreads();
   }

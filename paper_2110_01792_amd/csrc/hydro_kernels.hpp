@@ -35,7 +35,34 @@ struct StageArgs {
   int recon;             // 0 PPM, 1 PLM
   unsigned long long* smax;  // stage 2: max(|v| + c_s) of the new state (ordered bits), or NULL
   uint32_t* err;
+  double* reg;           // flux register over the faces bounding region [rlo, rhi), or NULL
+  int rlo[3], rhi[3];
+  double rw;             // register weight: each face adds rw * dt/2 * F
 };
+
+// Flux-register slot of variable v on face `side` (0 low, 1 high) of a region
+// for axis-d faces; (a, b) are the face's in-plane cell indices minus the
+// region's low corner, (a along the slower axis).  Layout: x faces
+// [v][side][k][j], then y faces [v][side][k][i], then z faces [v][side][j][i].
+__device__ __forceinline__ int64_t reg_slot(const int* lo, const int* hi, int d, int v, int side, int a, int b) {
+  const int64_t m0 = hi[0] - lo[0], m1 = hi[1] - lo[1], m2 = hi[2] - lo[2];
+  const int64_t nx = 2 * m1 * m2, ny = 2 * m0 * m2;
+  if (d == 0) return ((int64_t)(v * 2 + side) * m2 + a) * m1 + b;
+  if (d == 1) return 5 * nx + ((int64_t)(v * 2 + side) * m2 + a) * m0 + b;
+  return 5 * (nx + ny) + ((int64_t)(v * 2 + side) * m1 + a) * m0 + b;
+}
+
+// Add w * F (unrotated, 5 variables) at face `f` of axis d (between cells f-1
+// and f) of cell row (p, q) = the other two cell indices in increasing axis
+// order, if that face lies on the region's boundary.
+__device__ __forceinline__ void reg_add(double* reg, const int* lo, const int* hi, int d, int f, int p, int q,
+                                        double w, const double* F) {
+  const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
+  if ((f != lo[d] && f != hi[d]) || p < lo[d1] || p >= hi[d1] || q < lo[d2] || q >= hi[d2]) return;
+  const int side = f == hi[d] ? 1 : 0;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) reg[reg_slot(lo, hi, d, v, side, q - lo[d2], p - lo[d1])] += w * F[v];
+}
 
 // 1-D launch: consecutive hardware blocks are dealt round-robin to the 8
 // XCDs, each with its own L2.  Re-number them so that every XCD receives one
@@ -324,8 +351,9 @@ struct HydroSmem {
 
 // One tile of columns of one box: returns the thread's max(|v| + c_s) of the
 // new state (stage 2 with a.smax set), sets `bad` on a non-positive state.
-// NT threads (NT >= TX*TY); thread t owns column (t % TX, t / TX).
-template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE>
+// NT threads (NT >= TX*TY); thread t owns column (t % TX, t / TX).  REG:
+// compiled with the flux-register recording (a.reg), else without it.
+template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE, bool REG = false>
 __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, int tby, int tbz,
                                              HydroSmem<R, TX, TY, SPLIT>& sm, bool& bad_out) {
   using SM = HydroSmem<R, TX, TY, SPLIT>;
@@ -444,6 +472,10 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
 #pragma unroll
     for (int v = 0; v < 5; ++v) aRz[v] = rcur[v];
     load_cons(src_at(Uin, a.Ugh, b, i, j, z0 + 3), vs, cell(b, i, j, z0 + 3), cq);
+    if (REG && a.reg && z0 == 0) {  // face 0 belongs to the chunk starting at 0
+      const double F0[5] = {double(Fz[0]), double(Fz[2]), double(Fz[3]), double(Fz[1]), double(Fz[4])};
+      reg_add(a.reg, a.rlo, a.rhi, 2, 0, i, j, 0.5 * dt * a.rw, F0);
+    }
   }
 #pragma unroll
   for (int m = 0; m < HPT; ++m) load_halo<5>(hc[m], hc[m].src, chi, (int64_t)z0 * pz, vs, hq[m]);
@@ -513,6 +545,11 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
           hllc<R>(WL, WR, g, F);
 #pragma unroll
           for (int v = 0; v < 5; ++v) xF[v * XFS + it] = F[v];
+          // a face on a tile edge belongs to the tile on its high side, except the box's last face
+          if (REG && a.reg && (fx < tw || x0 + tw == b.n0)) {
+            const double Fd[5] = {double(F[0]), double(F[1]), double(F[2]), double(F[3]), double(F[4])};
+            reg_add(a.reg, a.rlo, a.rhi, 0, x0 + fx, y0 + yy, k, 0.5 * dt * a.rw, Fd);
+          }
         }
       }
     };
@@ -544,6 +581,10 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
           yF[2 * YFS + it] = F[1];
           yF[3 * YFS + it] = F[3];
           yF[4 * YFS + it] = F[4];
+          if (REG && a.reg && (fy < th || y0 + th == b.n1)) {
+            const double Fd[5] = {double(F[0]), double(F[2]), double(F[1]), double(F[3]), double(F[4])};
+            reg_add(a.reg, a.rlo, a.rhi, 1, y0 + fy, x0 + xx, k, 0.5 * dt * a.rw, Fd);
+          }
         }
       }
     };
@@ -593,6 +634,10 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
       // un-rotate (rho, w, u, v, E) fluxes to (rho, x, y, z, E)
       R Fn[5] = {Fk[0], Fk[2], Fk[3], Fk[1], Fk[4]};
       R Fo[5] = {Fz[0], Fz[2], Fz[3], Fz[1], Fz[4]};
+      if (REG && a.reg) {  // face k+1
+        const double Fd[5] = {double(Fn[0]), double(Fn[1]), double(Fn[2]), double(Fn[3]), double(Fn[4])};
+        reg_add(a.reg, a.rlo, a.rhi, 2, k + 1, i, j, 0.5 * dt * a.rw, Fd);
+      }
       const int64_t o = cell(b, i, j, k);
       double unew[5];
 #pragma unroll
@@ -637,12 +682,14 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
 // item per thread.
 constexpr int STX = 16, STY = 14, SNT = 256;
 
-template <class S, class R, int STAGE>
-__global__ __launch_bounds__(SNT) void stage_kernel(StageArgs<S, R> a) {
+// The recording variant is held to two blocks per CU (it would otherwise
+// take more than 256 registers and halve the occupancy).
+template <class S, class R, int STAGE, bool REG = false>
+__global__ __launch_bounds__(SNT, REG ? 2 : 1) void stage_kernel(StageArgs<S, R> a) {
   __shared__ HydroSmem<R, STX, STY, true> sm;
   const TileId tl = tile_of_block(a.gx, a.gy);
   bool bad = false;
-  const double smax = stage_tile<S, R, STX, STY, SNT, true, STAGE>(a, tl.bx, tl.by, tl.bz, sm, bad);
+  const double smax = stage_tile<S, R, STX, STY, SNT, true, STAGE, REG>(a, tl.bx, tl.by, tl.bz, sm, bad);
   if (bad) atomicOr(a.err, ERR_NEG);
   if (STAGE == 2 && a.smax) block_max_to<SNT>(smax, a.smax);
 }
