@@ -180,7 +180,7 @@ typedef struct {
 } qk_region;
 
 /* A flux register over a region is a caller-owned FP64 DEVICE array of
- * 10 (m1 m2 + m0 m2 + m0 m1) doubles, m = hi - lo: x faces [v][side][k][j],
+ * 10 (m1 m2 + m0 m2 + m0 m1) doubles (gas), m = hi - lo: x faces [v][side][k][j],
  * then y faces [v][side][k][i], then z faces [v][side][j][i], indices relative
  * to lo, side 0 the region's low face and 1 its high face, v the 5 gas
  * variables.  quokka_hydro_step_reg is quokka_hydro_step (no fused next dt)
@@ -190,6 +190,14 @@ typedef struct {
 qk_status quokka_hydro_step_reg(qk_ctx* ctx, const qk_box* box, void* U_gas, qk_precision prec,
                                 const qk_hydro_params* hp, const double* dt_dev, double dt_in,
                                 const qk_region* region, double* reg, double weight, void* stream);
+
+/* quokka_rad_step with a flux register over `region` for the radiation
+ * variables (E_r, F_x, F_y, F_z; the register layout above with 4 variables:
+ * 8 (m1 m2 + m0 m2 + m0 m1) doubles): every substep's two stages ADD
+ * weight * dt_sub/2 * F at the region's boundary faces. */
+qk_status quokka_rad_step_reg(qk_ctx* ctx, const qk_box* box, void* U_gas, void* U_rad, qk_precision prec,
+                              const qk_rad_params* rp, const double* dt_dev, const int32_t* nsub_dev, double dt_in,
+                              const qk_region* region, double* reg, double weight, void* stream);
 
 /* Coarse cells off + (I, J, K), 0 <= I < n_fine/2 (per axis), get the mean of
  * their 8 fine children (nvar variables; same precision on both levels).
@@ -212,7 +220,7 @@ qk_status quokka_prolong(qk_ctx* ctx, const qk_box* coarse, const void* U_c0, co
 /* Level synchronisation: `region` is the fine box's footprint on the coarse
  * level (fine extents = 2 (hi - lo)); reg_coarse is the coarse step's register
  * over it, reg_fine the sum of the fine steps' registers over the whole fine
- * box.  Each coarse cell just outside a boundary face gains
+ * box, both with nvar variables (5 gas, 4 radiation).  Each coarse cell just outside a boundary face gains
  * (R_coarse - mean of the 4 fine faces) / dx through the region's low face and
  * minus that through its high face. */
 qk_status quokka_reflux(qk_ctx* ctx, const qk_box* coarse, void* U_coarse, const qk_region* region,

@@ -73,6 +73,8 @@ def _load():
         "oracle_prolong": (None, [P(_Box), _D, _D, ctypes.c_double, P(_Box), _D, P(ctypes.c_int32), ctypes.c_int,
                                   ctypes.c_int]),
         "oracle_reflux": (None, [P(_Box), _D, P(_Region), _D, P(_Box), _D, ctypes.c_int]),
+        "oracle_rad_transport_substep_reg": (None, [P(_Box), _D, _D, P(_Rad), ctypes.c_double, P(_Region), _D,
+                                                     ctypes.c_double, P(_Stats)]),
         "oracle_exchange_series": (ctypes.c_double, [P(_Rad), ctypes.c_double, ctypes.c_double, ctypes.c_int64,
                                                      _D, _D, _D, ctypes.c_int64]),
         "oracle_rhd_step": (None, [P(_Box), _D, _D, P(_Rad), ctypes.c_double, P(_Stats)]),
@@ -322,3 +324,16 @@ def prolong(coarse, Uc0, Uc1, alpha, fine, Uf, off, nvar=5, interior=False):
 def reflux(coarse, Uc, lo, hi, reg_c, fine, reg_f, nvar=5):
     _load().oracle_reflux(ctypes.byref(_box(coarse)), _ptr(Uc), ctypes.byref(_region(lo, hi)), _ptr(reg_c),
                           ctypes.byref(_box(fine)), _ptr(reg_f), int(nvar))
+
+
+def rad_transport_substep_reg(b, Ur, Ug, p, dt, lo, hi, reg, weight=1.0):
+    """Radiation RK2 transport substep adding weight * dt/2 * F of both stages
+    at the faces bounding [lo, hi) to `reg` (4 variables)."""
+    _check(b, Ur, 4)
+    _check(b, Ug, 5)
+    assert reg.dtype == np.float64 and reg.size == region_size(lo, hi, 4)
+    st = _Stats()
+    _load().oracle_rad_transport_substep_reg(ctypes.byref(_box(b)), _ptr(Ur), _ptr(Ug), ctypes.byref(_rad(p)),
+                                             float(dt), ctypes.byref(_region(lo, hi)), _ptr(reg), float(weight),
+                                             ctypes.byref(st))
+    return _stats(st)

@@ -264,7 +264,7 @@ static double chi_tilde(const double* P, const double* u, size_t o, ptrdiff_t s)
     for (int j = (J0); j < (J1); ++j)                               \
       for (int i = (I0); i < (I1); ++i)
 
-static void record_region(const geo* g, const double* Fd, const ob_region* r, double* reg, double w);
+static void record_region(const geo* g, const double* Fd, int nvar, const ob_region* r, double* reg, double w);
 
 static void hydro_rhs(const ob_box* b, const double* U, double gam, int recon, double* L, ob_stats* st,
                       const ob_region* r, double* reg, double w);
@@ -392,7 +392,7 @@ static void hydro_rhs(const ob_box* b, const double* U, double gam, int recon, d
       L[v * vs + o] = -((t[0] + t[1]) + t[2]);
     }
   }
-  if (reg) record_region(&g, Fd, r, reg, w);
+  if (reg) record_region(&g, Fd, 5, r, reg, w);
   if (st) st->neg_cells += neg;
   free(W);
   free(cht);
@@ -403,30 +403,30 @@ static void hydro_rhs(const ob_box* b, const double* U, double gam, int recon, d
 }
 
 /* Add w * F at every face on the boundary of region r (face c-1/2 of axis d
- * is stored at cell c in Fd). */
-static void record_region(const geo* g, const double* Fd, const ob_region* r, double* reg, double w) {
+ * is stored at cell c in Fd, nvar variables per axis). */
+static void record_region(const geo* g, const double* Fd, int nvar, const ob_region* r, double* reg, double w) {
   const int m0 = r->hi[0] - r->lo[0], m1 = r->hi[1] - r->lo[1], m2 = r->hi[2] - r->lo[2];
   const size_t nx = (size_t)2 * m1 * m2, ny = (size_t)2 * m0 * m2;
   /* axes skipped as inactive (one cell, non-fixed) carry no fluxes here */
   if (!g->act[0] || !g->act[1] || !g->act[2]) return;
   double* rx = reg;
-  double* ry = reg + 5 * nx;
-  double* rz = reg + 5 * (nx + ny);
-  for (int v = 0; v < 5; ++v)
+  double* ry = reg + nvar * nx;
+  double* rz = reg + nvar * (nx + ny);
+  for (int v = 0; v < nvar; ++v)
     for (int side = 0; side < 2; ++side) {
       const int fx = side ? r->hi[0] : r->lo[0], fy = side ? r->hi[1] : r->lo[1], fz = side ? r->hi[2] : r->lo[2];
       for (int k = r->lo[2]; k < r->hi[2]; ++k)
         for (int j = r->lo[1]; j < r->hi[1]; ++j)
           rx[((size_t)(v * 2 + side) * m2 + (k - r->lo[2])) * m1 + (j - r->lo[1])] +=
-              w * Fd[(size_t)(0 * 5 + v) * g->vs + IX(g, fx, j, k)];
+              w * Fd[(size_t)(0 * nvar + v) * g->vs + IX(g, fx, j, k)];
       for (int k = r->lo[2]; k < r->hi[2]; ++k)
         for (int i = r->lo[0]; i < r->hi[0]; ++i)
           ry[((size_t)(v * 2 + side) * m2 + (k - r->lo[2])) * m0 + (i - r->lo[0])] +=
-              w * Fd[(size_t)(1 * 5 + v) * g->vs + IX(g, i, fy, k)];
+              w * Fd[(size_t)(1 * nvar + v) * g->vs + IX(g, i, fy, k)];
       for (int j = r->lo[1]; j < r->hi[1]; ++j)
         for (int i = r->lo[0]; i < r->hi[0]; ++i)
           rz[((size_t)(v * 2 + side) * m1 + (j - r->lo[1])) * m0 + (i - r->lo[0])] +=
-              w * Fd[(size_t)(2 * 5 + v) * g->vs + IX(g, i, j, fz)];
+              w * Fd[(size_t)(2 * nvar + v) * g->vs + IX(g, i, j, fz)];
     }
 }
 
@@ -619,19 +619,19 @@ void oracle_reflux(const ob_box* coarse, double* Uc, const ob_region* r, const d
         }
       for (int K = 0; K < m2; ++K)
         for (int I = 0; I < m0; ++I) {
-          const double c = reg_c[5 * cx + ((size_t)(v * 2 + side) * m2 + K) * m0 + I];
+          const double c = reg_c[nvar * cx + ((size_t)(v * 2 + side) * m2 + K) * m0 + I];
           double fs = 0.0;
           for (int q = 0; q < 4; ++q)
-            fs += reg_f[5 * fx + ((size_t)(v * 2 + side) * f2 + 2 * K + (q >> 1)) * f0 + 2 * I + (q & 1)];
+            fs += reg_f[nvar * fx + ((size_t)(v * 2 + side) * f2 + 2 * K + (q >> 1)) * f0 + 2 * I + (q & 1)];
           const int J = side ? r->hi[1] : r->lo[1] - 1;
           Uc[(size_t)v * gc.vs + IX(&gc, r->lo[0] + I, J, r->lo[2] + K)] += sg * (c - fs / 4.0) / coarse->dx[1];
         }
       for (int J = 0; J < m1; ++J)
         for (int I = 0; I < m0; ++I) {
-          const double c = reg_c[5 * (cx + cy) + ((size_t)(v * 2 + side) * m1 + J) * m0 + I];
+          const double c = reg_c[nvar * (cx + cy) + ((size_t)(v * 2 + side) * m1 + J) * m0 + I];
           double fs = 0.0;
           for (int q = 0; q < 4; ++q)
-            fs += reg_f[5 * (fx + fy) + ((size_t)(v * 2 + side) * f1 + 2 * J + (q >> 1)) * f0 + 2 * I + (q & 1)];
+            fs += reg_f[nvar * (fx + fy) + ((size_t)(v * 2 + side) * f1 + 2 * J + (q >> 1)) * f0 + 2 * I + (q & 1)];
           const int K = side ? r->hi[2] : r->lo[2] - 1;
           Uc[(size_t)v * gc.vs + IX(&gc, r->lo[0] + I, r->lo[1] + J, K)] += sg * (c - fs / 4.0) / coarse->dx[2];
         }
@@ -691,7 +691,15 @@ void oracle_hll_rad(double EL, const double FL[3], double ER, const double FR[3]
 /* Radiation transport right-hand side (Section 2.2.2): PPM (no flattening)
  * of E_r and the reduced flux f = F/(c E_r); per-face first-order fallback
  * when either reconstructed |f| exceeds 1; closure; HLL; unsplit divergence. */
+static void rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const ob_rad* p, double* L, ob_stats* st,
+                    const ob_region* r, double* reg, double w);
+
 void oracle_rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const ob_rad* p, double* L, ob_stats* st) {
+  rad_rhs(b, Ur, Ug, p, L, st, NULL, NULL, 0.0);
+}
+
+static void rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const ob_rad* p, double* L, ob_stats* st,
+                    const ob_region* r, double* reg, double w) {
   geo g = make_geo(b);
   const size_t vs = g.vs;
   double* Q = (double*)malloc(4 * vs * sizeof(double));
@@ -777,6 +785,7 @@ void oracle_rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const o
       L[v * vs + o] = -((t[0] + t[1]) + t[2]);
     }
   }
+  if (reg) record_region(&g, Fd, 4, r, reg, w);
   if (st) st->neg_cells += neg;
   free(Q);
   free(aL);
@@ -786,15 +795,20 @@ void oracle_rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const o
 
 void oracle_rad_transport_substep(const ob_box* b, double* Ur, const double* Ug, const ob_rad* p, double dt,
                                   ob_stats* st) {
+  oracle_rad_transport_substep_reg(b, Ur, Ug, p, dt, NULL, NULL, 0.0, st);
+}
+
+void oracle_rad_transport_substep_reg(const ob_box* b, double* Ur, const double* Ug, const ob_rad* p, double dt,
+                                      const ob_region* r, double* reg, double weight, ob_stats* st) {
   geo g = make_geo(b);
   const size_t nb = 4 * g.vs * sizeof(double);
   double* U1 = (double*)malloc(nb);
   double* Lb = (double*)calloc(4 * g.vs, sizeof(double));
   memcpy(U1, Ur, nb);
-  oracle_rad_rhs(b, Ur, Ug, p, Lb, st);
+  rad_rhs(b, Ur, Ug, p, Lb, st, r, reg, 0.5 * dt * weight);
   euler_interior(&g, 4, Ur, U1, Lb, dt);
   oracle_fill_ghosts(b, U1, 4);
-  oracle_rad_rhs(b, U1, Ug, p, Lb, st);
+  rad_rhs(b, U1, Ug, p, Lb, st, r, reg, 0.5 * dt * weight);
   rk2_interior(&g, 4, Ur, U1, Lb, dt);
   oracle_fill_ghosts(b, Ur, 4);
   free(U1);

@@ -68,12 +68,17 @@ void   oracle_batch_step(int32_t nbox, const ob_box* boxes, double* const* Ug, d
  * sum over RK stages of weight * dt/2 * F (FP64), laid out as
  *   x faces [v][side][k - lo2][j - lo1], then y faces [v][side][k - lo2][i - lo0],
  *   then z faces [v][side][j - lo1][i - lo0]   (side 0: face lo, 1: face hi),
- * 5 variables: 10 (m1 m2 + m0 m2 + m0 m1) doubles for m = hi - lo. */
+ * nvar variables (5 gas, 4 radiation): 2 nvar (m1 m2 + m0 m2 + m0 m1) doubles
+ * for m = hi - lo. */
 typedef struct {
   int32_t lo[3], hi[3];
 } ob_region;
 void   oracle_hydro_step_reg(const ob_box* b, double* U, double gamma, double cfl, double dt_in, int recon,
                              const ob_region* r, double* reg, double weight, ob_stats* st);
+/* One radiation RK2 transport substep adding weight * dt/2 * F of both stages
+ * at the faces bounding r to reg (4 variables: E_r, F_x, F_y, F_z). */
+void   oracle_rad_transport_substep_reg(const ob_box* b, double* Ur, const double* Ug, const ob_rad* p, double dt,
+                                        const ob_region* r, double* reg, double weight, ob_stats* st);
 /* Coarse cells off + (I/2) over the fine interior get the mean of their 8 children. */
 void   oracle_average_down(const ob_box* fine, const double* Uf, const ob_box* coarse, double* Uc,
                            const int32_t off[3], int nvar);

@@ -19,7 +19,8 @@ STATUS_NAMES = {0: "QK_OK", 1: "QK_EINVAL", 2: "QK_ENOMEM", 3: "QK_EHIP", 4: "QK
 EXPORTED = ("quokka_ctx_create", "quokka_ctx_destroy", "quokka_last_error", "quokka_fill_ghosts",
             "quokka_compute_dt", "quokka_hydro_step", "quokka_rad_step", "quokka_rhd_step", "quokka_batch_step",
             "quokka_sync_status", "quokka_newton_iter_max", "quokka_timing", "quokka_kernel_time", "quokka_batch_config",
-            "quokka_hydro_step_reg", "quokka_average_down", "quokka_prolong", "quokka_reflux")
+            "quokka_hydro_step_reg", "quokka_average_down", "quokka_prolong", "quokka_reflux",
+            "quokka_rad_step_reg")
 K_HYDRO_STAGE, K_FLATTEN, K_RAD_STAGE, K_RAD_COUPLE, K_GHOST, K_BATCH = range(6)
 
 
@@ -107,6 +108,8 @@ def load():
         "quokka_average_down": (ctypes.c_int, [V, P(QkBox), V, P(QkBox), V, P(I32), I32, ctypes.c_int, V]),
         "quokka_prolong": (ctypes.c_int, [V, P(QkBox), V, V, D, P(QkBox), V, P(I32), I32, I32, ctypes.c_int, V]),
         "quokka_reflux": (ctypes.c_int, [V, P(QkBox), V, P(QkRegion), V, P(QkBox), V, I32, ctypes.c_int, V]),
+        "quokka_rad_step_reg": (ctypes.c_int, [V, P(QkBox), V, V, ctypes.c_int, P(QkRadParams), V, V, D,
+                                               P(QkRegion), V, D, V]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -236,6 +239,20 @@ class Context:
                                                 ctypes.byref(hp), _ptr(dt_dev), float(dt),
                                                 ctypes.byref(make_region(lo, hi)), _ptr(reg), float(weight),
                                                 _stream(stream)))
+
+    def rad_step_reg(self, b, Ug, Ur, rp, lo, hi, reg, dt, weight=1.0, stream=None):
+        """Radiation step over host dt (ceil(dt / dt_r) substeps) adding
+        weight * dt_sub/2 * F of every stage at the faces bounding [lo, hi)
+        to the FP64 device register `reg` (4 variables)."""
+        import torch
+        _check_state(Ug, b, 5)
+        _check_state(Ur, b, 4)
+        if reg.dtype != torch.float64 or reg.numel() != region_size(lo, hi, 4) or not reg.is_cuda:
+            raise ValueError("register must be a float64 device tensor of region_size(lo, hi, 4) elements")
+        self._ok(self.lib.quokka_rad_step_reg(self.h, ctypes.byref(make_box(b)), _ptr(Ug), _ptr(Ur), _prec_of(Ug),
+                                              ctypes.byref(rp), None, None, float(dt),
+                                              ctypes.byref(make_region(lo, hi)), _ptr(reg), float(weight),
+                                              _stream(stream)))
 
     def average_down(self, fb, Uf, cb, Uc, off, nvar=5, stream=None):
         _check_state(Uf, fb, nvar)

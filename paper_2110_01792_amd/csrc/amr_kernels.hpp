@@ -99,10 +99,10 @@ __global__ __launch_bounds__(256) void reflux_kernel(S* __restrict__ Uc, DevBox 
     // in-plane coarse indices (a slower, b faster) of this face
     const int mb = d == 0 ? m1 : m0;
     const int A = (int)(e / mb), B = (int)(e % mb);
-    const double cval = rc[reg_slot(lo, hi, d, v, side, A, B)];
+    const double cval = rc[reg_slot(lo, hi, d, v, side, A, B, nvar)];
     double fs = 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) fs += rf[reg_slot(flo, fhi, d, v, side, 2 * A + (q >> 1), 2 * B + (q & 1))];
+    for (int q = 0; q < 4; ++q) fs += rf[reg_slot(flo, fhi, d, v, side, 2 * A + (q >> 1), 2 * B + (q & 1), nvar)];
     const double corr = (side ? -1.0 : 1.0) * (cval - fs / 4.0) / dxs[d];
     int x[3];
     const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;

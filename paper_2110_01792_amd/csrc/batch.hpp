@@ -133,6 +133,7 @@ __global__ __launch_bounds__(TX* TY, 2) void batch_rad_kernel(const BatchBox<S, 
     a.gx = a.gy = 1;
     a.err = err;
     a.iter_max = iter_max;
+    a.reg = nullptr;
     itmax = max(itmax, rad_tile<S, R, TX, TY, TX * TY, false, STAGE>(a, w.bx, w.by, w.bz, N, sm, bad, nfail));
     __syncthreads();
   }

@@ -40,28 +40,30 @@ struct StageArgs {
   double rw;             // register weight: each face adds rw * dt/2 * F
 };
 
-// Flux-register slot of variable v on face `side` (0 low, 1 high) of a region
-// for axis-d faces; (a, b) are the face's in-plane cell indices minus the
-// region's low corner, (a along the slower axis).  Layout: x faces
+// Flux-register slot of variable v (of nv) on face `side` (0 low, 1 high) of
+// a region for axis-d faces; (a, b) are the face's in-plane cell indices minus
+// the region's low corner, (a along the slower axis).  Layout: x faces
 // [v][side][k][j], then y faces [v][side][k][i], then z faces [v][side][j][i].
-__device__ __forceinline__ int64_t reg_slot(const int* lo, const int* hi, int d, int v, int side, int a, int b) {
+__device__ __forceinline__ int64_t reg_slot(const int* lo, const int* hi, int d, int v, int side, int a, int b,
+                                            int nv) {
   const int64_t m0 = hi[0] - lo[0], m1 = hi[1] - lo[1], m2 = hi[2] - lo[2];
   const int64_t nx = 2 * m1 * m2, ny = 2 * m0 * m2;
   if (d == 0) return ((int64_t)(v * 2 + side) * m2 + a) * m1 + b;
-  if (d == 1) return 5 * nx + ((int64_t)(v * 2 + side) * m2 + a) * m0 + b;
-  return 5 * (nx + ny) + ((int64_t)(v * 2 + side) * m1 + a) * m0 + b;
+  if (d == 1) return nv * nx + ((int64_t)(v * 2 + side) * m2 + a) * m0 + b;
+  return nv * (nx + ny) + ((int64_t)(v * 2 + side) * m1 + a) * m0 + b;
 }
 
-// Add w * F (unrotated, 5 variables) at face `f` of axis d (between cells f-1
-// and f) of cell row (p, q) = the other two cell indices in increasing axis
-// order, if that face lies on the region's boundary.
+// Add w * F (unrotated, NV variables) at face `f` of axis d (between cells
+// f-1 and f) of cell row (p, q) = the other two cell indices in increasing
+// axis order, if that face lies on the region's boundary.
+template <int NV>
 __device__ __forceinline__ void reg_add(double* reg, const int* lo, const int* hi, int d, int f, int p, int q,
                                         double w, const double* F) {
   const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
   if ((f != lo[d] && f != hi[d]) || p < lo[d1] || p >= hi[d1] || q < lo[d2] || q >= hi[d2]) return;
   const int side = f == hi[d] ? 1 : 0;
 #pragma unroll
-  for (int v = 0; v < 5; ++v) reg[reg_slot(lo, hi, d, v, side, q - lo[d2], p - lo[d1])] += w * F[v];
+  for (int v = 0; v < NV; ++v) reg[reg_slot(lo, hi, d, v, side, q - lo[d2], p - lo[d1], NV)] += w * F[v];
 }
 
 // 1-D launch: consecutive hardware blocks are dealt round-robin to the 8
@@ -474,7 +476,7 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
     load_cons(src_at(Uin, a.Ugh, b, i, j, z0 + 3), vs, cell(b, i, j, z0 + 3), cq);
     if (REG && a.reg && z0 == 0) {  // face 0 belongs to the chunk starting at 0
       const double F0[5] = {double(Fz[0]), double(Fz[2]), double(Fz[3]), double(Fz[1]), double(Fz[4])};
-      reg_add(a.reg, a.rlo, a.rhi, 2, 0, i, j, 0.5 * dt * a.rw, F0);
+      reg_add<5>(a.reg, a.rlo, a.rhi, 2, 0, i, j, 0.5 * dt * a.rw, F0);
     }
   }
 #pragma unroll
@@ -548,7 +550,7 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
           // a face on a tile edge belongs to the tile on its high side, except the box's last face
           if (REG && a.reg && (fx < tw || x0 + tw == b.n0)) {
             const double Fd[5] = {double(F[0]), double(F[1]), double(F[2]), double(F[3]), double(F[4])};
-            reg_add(a.reg, a.rlo, a.rhi, 0, x0 + fx, y0 + yy, k, 0.5 * dt * a.rw, Fd);
+            reg_add<5>(a.reg, a.rlo, a.rhi, 0, x0 + fx, y0 + yy, k, 0.5 * dt * a.rw, Fd);
           }
         }
       }
@@ -583,7 +585,7 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
           yF[4 * YFS + it] = F[4];
           if (REG && a.reg && (fy < th || y0 + th == b.n1)) {
             const double Fd[5] = {double(F[0]), double(F[2]), double(F[1]), double(F[3]), double(F[4])};
-            reg_add(a.reg, a.rlo, a.rhi, 1, y0 + fy, x0 + xx, k, 0.5 * dt * a.rw, Fd);
+            reg_add<5>(a.reg, a.rlo, a.rhi, 1, y0 + fy, x0 + xx, k, 0.5 * dt * a.rw, Fd);
           }
         }
       }
@@ -636,7 +638,7 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
       R Fo[5] = {Fz[0], Fz[2], Fz[3], Fz[1], Fz[4]};
       if (REG && a.reg) {  // face k+1
         const double Fd[5] = {double(Fn[0]), double(Fn[1]), double(Fn[2]), double(Fn[3]), double(Fn[4])};
-        reg_add(a.reg, a.rlo, a.rhi, 2, k + 1, i, j, 0.5 * dt * a.rw, Fd);
+        reg_add<5>(a.reg, a.rlo, a.rhi, 2, k + 1, i, j, 0.5 * dt * a.rw, Fd);
       }
       const int64_t o = cell(b, i, j, k);
       double unew[5];

@@ -38,6 +38,9 @@ struct RadStageArgs {
   int zc, gx, gy;
   uint32_t* err;
   uint32_t* iter_max;
+  double* reg;             // flux register over the faces bounding [rlo, rhi), or NULL
+  int rlo[3], rhi[3];
+  double rw;               // register weight: each face adds rw * dt_sub/2 * F
 };
 
 // HLL flux of (E, F) along axis d between face states (E, f), |f| = nL, nR
@@ -192,8 +195,9 @@ struct RadSmem {
 
 // One tile of columns of one box for substep `a.sub` (the caller has checked
 // that the substep is active).  Returns the largest exchange iteration count.
-// NT threads (NT >= TX*TY); thread t owns column (t % TX, t / TX).
-template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE>
+// NT threads (NT >= TX*TY); thread t owns column (t % TX, t / TX).  REG:
+// compiled with the flux-register recording (a.reg).
+template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE, bool REG = false>
 __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tbx, int tby, int tbz, int N,
                                              RadSmem<R, TX, TY, SPLIT>& sm, bool& bad_out, bool& nfail_out) {
   using SM = RadSmem<R, TX, TY, SPLIT>;
@@ -331,6 +335,10 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
 #pragma unroll
     for (int v = 0; v < 4; ++v) aRz[v] = rcur[v];
     rz_k1 = rr;
+    if (REG && a.reg && z0 == 0) {  // face 0 belongs to the chunk starting at 0
+      const double F0[4] = {double(Fz[0]), double(Fz[1]), double(Fz[2]), double(Fz[3])};
+      reg_add<4>(a.reg, a.rlo, a.rhi, 2, 0, i, j, 0.5 * dt * a.rw, F0);
+    }
     load4(src_at(Uin, a.Ugh, b, i, j, z0 + 3), cell(b, i, j, z0 + 3), cq);
   }
 #pragma unroll
@@ -413,6 +421,10 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
           rad_face<R>(sl, sr, cl, cr, rl, rr, R(b.dx0), 0, p, c, chat, ratio, cc, F);
 #pragma unroll
           for (int v = 0; v < 4; ++v) xF[v * XFS + it] = F[v];
+          if (REG && a.reg && (fx < tw || x0 + tw == b.n0)) {
+            const double Fd[4] = {double(F[0]), double(F[1]), double(F[2]), double(F[3])};
+            reg_add<4>(a.reg, a.rlo, a.rhi, 0, x0 + fx, y0 + yy, k, 0.5 * dt * a.rw, Fd);
+          }
         }
       }
     };
@@ -444,6 +456,10 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
           rad_face<R>(sl, sr, cl, cr, rl, rr, R(b.dx1), 1, p, c, chat, ratio, cc, F);
 #pragma unroll
           for (int v = 0; v < 4; ++v) yF[v * YFS + it] = F[v];
+          if (REG && a.reg && (fy < th || y0 + th == b.n1)) {
+            const double Fd[4] = {double(F[0]), double(F[1]), double(F[2]), double(F[3])};
+            reg_add<4>(a.reg, a.rlo, a.rhi, 1, y0 + fy, x0 + xx, k, 0.5 * dt * a.rw, Fd);
+          }
         }
       }
     };
@@ -496,6 +512,10 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
         ck1[v] = w[v][2];
       }
       rad_face<R>(aRz, aLn, ck, ck1, rz_k, rz_k1, R(b.dx2), 2, p, c, chat, ratio, cc, Fk);
+      if (REG && a.reg) {  // face k+1
+        const double Fd[4] = {double(Fk[0]), double(Fk[1]), double(Fk[2]), double(Fk[3])};
+        reg_add<4>(a.reg, a.rlo, a.rhi, 2, k + 1, i, j, 0.5 * dt * a.rw, Fd);
+      }
       const int64_t o = cell(b, i, j, k);
       double un[4];
 #pragma unroll
@@ -524,14 +544,14 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
   return itmax;
 }
 
-template <class S, class R, int STAGE>
+template <class S, class R, int STAGE, bool REG = false>
 __global__ __launch_bounds__(SNT, 2) void rad_stage_kernel(RadStageArgs<S, R> a) {
   const int N = a.nsub_ptr ? *a.nsub_ptr : a.nsub_val;
   if (a.sub >= N) return;  // block-uniform: the whole grid skips unused substeps
   __shared__ RadSmem<R, STX, STY, true> sm;
   const TileId tl = tile_of_block(a.gx, a.gy);
   bool bad = false, nfail = false;
-  const uint32_t itmax = rad_tile<S, R, STX, STY, SNT, true, STAGE>(a, tl.bx, tl.by, tl.bz, N, sm, bad, nfail);
+  const uint32_t itmax = rad_tile<S, R, STX, STY, SNT, true, STAGE, REG>(a, tl.bx, tl.by, tl.bz, N, sm, bad, nfail);
   if (bad) atomicOr(a.err, ERR_NEG);
   if (nfail) atomicOr(a.err, ERR_NEWTON);
   if (STAGE == 2) block_umax_to<SNT>(itmax, a.iter_max);

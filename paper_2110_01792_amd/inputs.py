@@ -316,9 +316,13 @@ def to_f32_and_back(U):
 # rho = 1 + 0.2 s1, P = 1 + 0.1 s2, v_d = 0.2 s_{3+d} (s_i = sum of 4 modes),
 # gamma 5/3.  Draws: 5 mode sets.
 # ---------------------------------------------------------------------------
-def two_level(n=16, m=16, off=(4, 4, 4), seed=61, gamma=5.0 / 3.0, ng=4):
+def two_level(n=16, m=16, off=(4, 4, 4), seed=61, gamma=5.0 / 3.0, ng=4, rad=False):
+    """With rad=True also radiation states on both levels (E_r = (1 + 0.2 s6)^4,
+    F = 0.2 c E_r (s7, s8, s9) / 4 with c = 1000; two more draws of 4 mode sets)
+    and radiation parameters (chat 50, kappa 0: transport only) are returned."""
     rng = np.random.default_rng(seed)
     modes = [_modes(rng) for _ in range(5)]
+    rmodes = [_modes(rng) for _ in range(4)] if rad else []
     cb = make_box(n, ng=ng, bc=PERIODIC)
     dxf = cb.dx[0] / 2.0
     fo = tuple(off[d] * cb.dx[d] for d in range(3))
@@ -332,4 +336,20 @@ def two_level(n=16, m=16, off=(4, 4, 4), seed=61, gamma=5.0 / 3.0, ng=4):
         U[b.interior()] = _conserved(1.0 + 0.2 * s[0], 0.2 * s[2], 0.2 * s[3], 0.2 * s[4], 1.0 + 0.1 * s[1], gamma)
         return U
 
-    return cb, fill(cb), fb, fill(fb), tuple(off), {"gamma": gamma, "cfl": 0.3}
+    def fill_rad(b, c):
+        z, y, x = cell_centres(b)
+        full = np.ones((b.n[2], b.n[1], b.n[0]))
+        s = [_mode_sum(k, p, z, y, x) * full for (k, p) in rmodes]
+        E = (1.0 + 0.2 * s[0]) ** 4
+        U = _alloc(b, 4)
+        I = b.interior()
+        U[(0,) + I[1:]] = E
+        for d in range(3):
+            U[(1 + d,) + I[1:]] = 0.2 * c * E * s[1 + d] / 4.0
+        return U
+
+    hp = {"gamma": gamma, "cfl": 0.3}
+    if not rad:
+        return cb, fill(cb), fb, fill(fb), tuple(off), hp
+    p = rad_params(50.0, gamma=gamma, kappa_P=0.0, kappa_R=0.0)
+    return (cb, fill(cb), fill_rad(cb, p["c"]), fb, fill(fb), fill_rad(fb, p["c"]), tuple(off), hp, p)

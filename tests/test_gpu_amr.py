@@ -8,7 +8,8 @@ import pytest
 import oracle
 from paper_2110_01792_amd import binding as qb
 from paper_2110_01792_amd import inputs
-from tests.amr_runs import composite_totals, coarse_totals, region_size, two_level_step
+from tests.amr_runs import (composite_totals, composite_totals_n, coarse_totals, coarse_totals_n, region_size,
+                            two_level_rad_step, two_level_step)
 from tests.gpu_util import dev, host, rel_linf
 from tests.test_oracle_amr import OracleAMR
 
@@ -47,14 +48,17 @@ class GpuAMR:
     def hydro_step_reg(self, b, U, gamma, cfl, dt, lo, hi, reg):
         self.ctx.hydro_step_reg(b, U, qb.hydro_params(gamma, cfl), lo, hi, reg, dt=dt)
 
-    def prolong(self, cb, U0, U1, alpha, fb, Uf, off, interior=False):
-        self.ctx.prolong(cb, U0, U1, alpha, fb, Uf, off, interior=interior)
+    def prolong(self, cb, U0, U1, alpha, fb, Uf, off, interior=False, nvar=5):
+        self.ctx.prolong(cb, U0, U1, alpha, fb, Uf, off, nvar=nvar, interior=interior)
 
-    def average_down(self, fb, Uf, cb, Uc, off):
-        self.ctx.average_down(fb, Uf, cb, Uc, off)
+    def average_down(self, fb, Uf, cb, Uc, off, nvar=5):
+        self.ctx.average_down(fb, Uf, cb, Uc, off, nvar=nvar)
 
-    def reflux(self, cb, Uc, lo, hi, reg_c, fb, reg_f):
-        self.ctx.reflux(cb, Uc, lo, hi, reg_c, fb, reg_f)
+    def reflux(self, cb, Uc, lo, hi, reg_c, fb, reg_f, nvar=5):
+        self.ctx.reflux(cb, Uc, lo, hi, reg_c, fb, reg_f, nvar=nvar)
+
+    def rad_step_reg(self, b, Ug, Ur, p, dt, lo, hi, reg):
+        self.ctx.rad_step_reg(b, Ug, Ur, qb.rad_params(p), lo, hi, reg, dt)
 
 
 def test_register_matches_oracle(ctx):
@@ -116,6 +120,28 @@ def test_two_level_step_matches_oracle_and_conserves(ctx):
         assert np.all(rel_linf(host(Fd), Fo, fb) <= TOL)
     t1 = coarse_totals(cb, host(Cd))
     assert np.all(np.abs(t1 - t0) / np.abs(t0).max() < 1e-14)
+
+
+def test_radiation_two_level_step_matches_oracle_and_conserves(ctx):
+    """Radiation on two levels (transport only, kappa = 0): registers recorded
+    by the radiation stage kernel over every substep, prolongation and
+    average-down of 4 variables, reflux; GPU against the oracle and the
+    totals of E_r and F kept to round-off."""
+    cb, Gc, Rc, fb, Gf, Rf, off, hp, p = inputs.two_level(rad=True)
+    oracle.average_down(fb, Rf, cb, Rc, off, nvar=4)
+    oracle.average_down(fb, Gf, cb, Gc, off, nvar=5)
+    t0 = composite_totals_n(cb, Rc, fb, Rf, off)
+    d = [dev(x) for x in (Gc, Rc, Gf, Rf)]
+    o = [x.copy() for x in (Gc, Rc, Gf, Rf)]
+    A = GpuAMR(ctx)
+    for _ in range(2):
+        two_level_rad_step(A, cb, d[0], d[1], fb, d[2], d[3], off, p)
+        two_level_rad_step(OracleAMR, cb, o[0], o[1], fb, o[2], o[3], off, p)
+        assert ctx.sync_status() == qb.QK_OK
+        for x, y, b in zip(d, o, (cb, cb, fb, fb)):
+            assert np.all(rel_linf(host(x), y, b) <= TOL)
+    t1 = coarse_totals_n(cb, host(d[1]))
+    assert np.all(np.abs(t1 - t0) / np.abs(t0[0]) < 1e-13)
 
 
 def test_amr_argument_errors(ctx):

@@ -5,7 +5,8 @@ import numpy as np
 
 import oracle
 from paper_2110_01792_amd import inputs
-from tests.amr_runs import composite_totals, coarse_totals, two_level_step
+from tests.amr_runs import (composite_totals, composite_totals_n, coarse_totals, coarse_totals_n, region_size,
+                            two_level_rad_step, two_level_step)
 
 
 class OracleAMR:
@@ -23,16 +24,25 @@ class OracleAMR:
         oracle.hydro_step_reg(b, U, gamma, cfl, dt, lo, hi, reg)
 
     @staticmethod
-    def prolong(cb, U0, U1, alpha, fb, Uf, off, interior=False):
-        oracle.prolong(cb, U0, U1, alpha, fb, Uf, off, interior=interior)
+    def prolong(cb, U0, U1, alpha, fb, Uf, off, interior=False, nvar=5):
+        oracle.prolong(cb, U0, U1, alpha, fb, Uf, off, nvar=nvar, interior=interior)
 
     @staticmethod
-    def average_down(fb, Uf, cb, Uc, off):
-        oracle.average_down(fb, Uf, cb, Uc, off)
+    def average_down(fb, Uf, cb, Uc, off, nvar=5):
+        oracle.average_down(fb, Uf, cb, Uc, off, nvar=nvar)
 
     @staticmethod
-    def reflux(cb, Uc, lo, hi, reg_c, fb, reg_f):
-        oracle.reflux(cb, Uc, lo, hi, reg_c, fb, reg_f)
+    def reflux(cb, Uc, lo, hi, reg_c, fb, reg_f, nvar=5):
+        oracle.reflux(cb, Uc, lo, hi, reg_c, fb, reg_f, nvar=nvar)
+
+    @staticmethod
+    def rad_step_reg(b, Ug, Ur, p, dt, lo, hi, reg):
+        """ceil(dt / dt_r) substeps of transport (with the register) and coupling."""
+        dt_r = p["cfl"] * min(b.dx) / p["chat"]
+        n = int(np.ceil(dt / dt_r))
+        for _ in range(n):
+            oracle.rad_transport_substep_reg(b, Ur, Ug, p, dt / n, lo, hi, reg)
+            oracle.exchange_all(b, Ug, Ur, p, dt / n)
 
 
 def test_average_down_is_the_mean_of_children():
@@ -85,6 +95,47 @@ def test_prolongation_time_interpolation():
     oracle.prolong(cb, Uc, U1, 0.5, fb, m, off, interior=True)
     assert np.array_equal(a, b_)
     assert np.allclose(m, 1.25 * a, rtol=1e-14, atol=1e-15)
+
+
+def test_radiation_register_matches_change_of_the_region_total():
+    """As below for the radiation variables (no coupling: kappa = 0)."""
+    cb, Gc, Rc, fb, Gf, Rf, off, hp, p = inputs.two_level(rad=True)
+    oracle.fill_ghosts(cb, Gc)
+    oracle.fill_ghosts(cb, Rc)
+    lo, hi = (2, 6, 3), (12, 13, 10)
+    reg = np.zeros(region_size(lo, hi, 4))
+    g = cb.ng
+    sl = (slice(None), slice(g + lo[2], g + hi[2]), slice(g + lo[1], g + hi[1]), slice(g + lo[0], g + hi[0]))
+    before = Rc[sl].reshape(4, -1).sum(axis=1)
+    oracle.rad_transport_substep_reg(cb, Rc, Gc, p, 0.5 * p["cfl"] * cb.dx[0] / p["chat"], lo, hi, reg)
+    after = Rc[sl].reshape(4, -1).sum(axis=1)
+    m = [hi[d] - lo[d] for d in range(3)]
+    nx, ny = 2 * m[1] * m[2], 2 * m[0] * m[2]
+    rx = reg[:4 * nx].reshape(4, 2, -1).sum(axis=2)
+    ry = reg[4 * nx:4 * (nx + ny)].reshape(4, 2, -1).sum(axis=2)
+    rz = reg[4 * (nx + ny):].reshape(4, 2, -1).sum(axis=2)
+    net = -((rx[:, 1] - rx[:, 0]) + (ry[:, 1] - ry[:, 0]) + (rz[:, 1] - rz[:, 0])) / cb.dx[0]
+    assert np.allclose(after - before, net, rtol=1e-10, atol=1e-12 * np.abs(before).max())
+
+
+def test_two_level_radiation_conserves_only_with_reflux():
+    """Level synchronisation of the radiation subsystem (Section 2.2): with
+    transport only, the coarse totals of E_r and F after sync equal the
+    composite totals before (round-off) only when the radiation register is
+    refluxed."""
+    for reflux in (True, False):
+        cb, Gc, Rc, fb, Gf, Rf, off, hp, p = inputs.two_level(rad=True)
+        oracle.average_down(fb, Rf, cb, Rc, off, nvar=4)
+        oracle.average_down(fb, Gf, cb, Gc, off, nvar=5)
+        t0 = composite_totals_n(cb, Rc, fb, Rf, off)
+        for _ in range(2):
+            two_level_rad_step(OracleAMR, cb, Gc, Rc, fb, Gf, Rf, off, p, reflux=reflux)
+        t1 = coarse_totals_n(cb, Rc)
+        err = np.abs(t1 - t0) / np.abs(t0[0])
+        if reflux:
+            assert np.all(err < 1e-13), err
+        else:
+            assert np.max(err) > 1e-9, err
 
 
 def test_flux_register_matches_change_of_the_region_total():
