@@ -217,8 +217,4 @@ __device__ __forceinline__ void eddington_row(R fx, R fy, R fz, R fn, int d, int
   Tdd = d == 0 ? Tx : (d == 1 ? Ty : Tz);
 }
 
-struct RadConst {
-  double c, chat, ratio /*chat/c*/, cc /*c*chat*/;
-};
-
 }  // namespace qk

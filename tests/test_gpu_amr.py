@@ -155,3 +155,25 @@ def test_amr_argument_errors(ctx):
     with pytest.raises(qb.QuokkaError) as e:
         ctx.hydro_step_reg(cb, Cd, qb.hydro_params(p["gamma"], p["cfl"]), (0, 0, 0), (4, 4, 40), reg, dt=1e-3)
     assert e.value.status == qb.QK_EINVAL
+
+
+def test_amr_operations_in_fp32(ctx):
+    """Mixed-precision (FP32) state through prolongation and average-down
+    (FP64 arithmetic inside, one FP32 rounding on store) against the FP64
+    oracle on the same FP32-rounded data."""
+    torch = pytest.importorskip("torch")
+    cb, Uc, fb, Uf, off, p = inputs.two_level()
+    oracle.fill_ghosts(cb, Uc)
+    Uc = inputs.to_f32_and_back(Uc)
+    Uf = inputs.to_f32_and_back(Uf)
+    fo = Uf.copy()
+    oracle.prolong(cb, Uc, Uc, 0.0, fb, fo, off, interior=True)
+    fd = dev(Uf, torch.float32)
+    cd = dev(Uc, torch.float32)
+    ctx.prolong(cb, cd, cd, 0.0, fb, fd, off, interior=True)
+    assert np.all(rel_linf(host(fd), fo, fb) <= 2e-7)
+    co = Uc.copy()
+    oracle.average_down(fb, Uf, cb, co, off)
+    cd = dev(Uc, torch.float32)
+    ctx.average_down(fb, dev(Uf, torch.float32), cb, cd, off)
+    assert np.all(rel_linf(host(cd), co, cb) <= 2e-7)

@@ -78,6 +78,20 @@ def test_batch_hydro_only_equals_single_box_runs_bitwise(ctx):
         assert np.array_equal(host(U), gG[k]), (k, b.n)
 
 
+def test_batch_plm_equals_single_box_runs_bitwise(ctx):
+    """PLM (reconstruction 1) through the batched level: each box equals the
+    same box advanced alone with the level dt."""
+    boxes, Ugs, Urs, p, hp = inputs.batch_level(nbox=6, seed=35, edges=(8, 16, 24), rad_fraction=0.0)
+    G = [dev(u) for u in Ugs]
+    hpp = qb.hydro_params(hp["gamma"], hp["cfl"], recon=1)
+    dt = ctx.batch_step(boxes, G, [None] * len(boxes), hpp, qb.rad_params(p))
+    assert ctx.sync_status() == qb.QK_OK
+    for k, b in enumerate(boxes):
+        U = dev(Ugs[k])
+        ctx.hydro_step(b, U, hpp, dt=dt)
+        assert np.array_equal(host(U), host(G[k])), (k, b.n)
+
+
 def test_batch_full_level_sampled_against_oracle(ctx):
     """The benchmark's batched level at full size (600 boxes, edges
     {8..64}, half RHD): every box advanced on the GPU in one graph; a sample
