@@ -85,6 +85,15 @@ def test_shock_256_full_size(ctx):
     check(gpu_steps(ctx, b, U, p["gamma"], p["cfl"], 1), oracle_steps(b, U, p["gamma"], p["cfl"], 1), b)
 
 
+@pytest.mark.parametrize("recon", [0, 1])
+def test_sedov_blast(ctx, recon):
+    """The paper's hydro performance problem (Sedov blast, gamma 5/3, CFL 0.25,
+    periodic) at 48^3: a strong point explosion, 4 steps, PPM and PLM."""
+    b, U, p = inputs.sedov(n=48)
+    check(gpu_steps(ctx, b, U, p["gamma"], p["cfl"], 4, recon=recon),
+          oracle_steps(b, U, p["gamma"], p["cfl"], 4, recon=recon), b)
+
+
 def test_mixed_boundaries_and_fixed_ghosts(ctx):
     """Periodic x, outflow y, fixed z (caller ghosts held)."""
     b0, U0, p = inputs.hydro_smooth(n=24, seed=4)
