@@ -759,6 +759,8 @@ static void rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const o
           FRv[m] = c * ER * fR[m];
         }
       }
+      /* optical-depth factor: the paper gives its purpose, not its formula
+         (a reading; parity partly pinned by the radiation pressure tube) */
       double eps = 1.0;
       if (p->tau_correction && !fallback) {
         const double tau = b->dx[d] * p->kappa_R * (0.5 * (Ug[ol] + Ug[o]));
