@@ -8,6 +8,12 @@
  * smoke check and the benchmark's CPU-baseline leg may load it.  It shares no
  * code, header, constant or helper with the GPU library.
  *
+ * Pins: the tests check every function against closed forms, invariants, the
+ * paper's printed results or exact solutions.  One part is only partly
+ * pinned: the optical-depth factor of the radiation HLL flux, whose formula
+ * the paper does not give (its value is a reading; the radiation pressure
+ * tube runs with it active and holds the paper's accuracy in its interior).
+ *
  * Array layout used by every entry point: one contiguous float64 array per
  * state, shape (nvar, nz+2ng, ny+2ng, nx+2ng), x fastest.  Gas state has
  * nvar = 5 (rho, rho*vx, rho*vy, rho*vz, E); radiation state has nvar = 4
