@@ -85,6 +85,17 @@ def test_shock_256_full_size(ctx):
     check(gpu_steps(ctx, b, U, p["gamma"], p["cfl"], 1), oracle_steps(b, U, p["gamma"], p["cfl"], 1), b)
 
 
+def test_shock_256_full_step_count(ctx):
+    """The benchmark workload over its full 20 steps (each path its own CFL dt),
+    compared everywhere after the last step."""
+    b, U, p = inputs.hydro_shock(n=256)
+    oracle.set_threads(0)
+    g = gpu_steps(ctx, b, U, p["gamma"], p["cfl"], 20)
+    o = oracle_steps(b, U, p["gamma"], p["cfl"], 20)
+    print("max relative L-inf after 20 steps:", rel_linf(g, o, b).max(), flush=True)
+    check(g, o, b)
+
+
 @pytest.mark.parametrize("recon", [0, 1])
 def test_sedov_blast(ctx, recon):
     """The paper's hydro performance problem (Sedov blast, gamma 5/3, CFL 0.25,
