@@ -302,23 +302,23 @@ def main():
     h64, b, p = bench_hydro(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float64)
     log("hydro FP64:", h64)
     log("RHD FP64 256^3 ...")
-    r64 = bench_rhd(ctx, qb, inputs, torch, max(2, args.steps // 4), max(1, args.warmup // 2), torch.float64)
+    r64 = bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float64)
     log("RHD FP64:", r64)
     log("paper workloads: Sedov 256^3 PPM hydro, RHD 256^3 PLM ...")
     sed64, _, _ = bench_hydro(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float64, workload="sedov")
-    plm64 = bench_rhd(ctx, qb, inputs, torch, max(2, args.steps // 4), max(1, args.warmup // 2), torch.float64,
+    plm64 = bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float64,
                       recon=1)
     log("Sedov:", sed64, "RHD PLM:", plm64)
     log("mixed ...")
     h32, _, _ = bench_hydro(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float32)
-    r32 = bench_rhd(ctx, qb, inputs, torch, max(2, args.steps // 4), max(1, args.warmup // 2), torch.float32)
+    r32 = bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float32)
     h32["error_vs_f64_20_steps"] = mixed_error_hydro(ctx, qb, inputs, torch)
     r32["error_vs_f64"] = mixed_error_rhd(ctx, qb, inputs, torch)
     log("mixed hydro:", h32)
     log("mixed RHD:", r32)
     log("batched ...")
-    b64 = bench_batch(ctx, qb, inputs, torch, max(2, args.steps // 4), torch.float64)
-    b32 = bench_batch(ctx, qb, inputs, torch, max(2, args.steps // 4), torch.float32)
+    b64 = bench_batch(ctx, qb, inputs, torch, args.steps, torch.float64)
+    b32 = bench_batch(ctx, qb, inputs, torch, args.steps, torch.float32)
     log("batch:", b64, b32)
 
     # The fused stage does ~1075 FP64 operations per ~100 HBM bytes (10.8
