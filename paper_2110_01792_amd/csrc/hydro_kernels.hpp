@@ -325,11 +325,29 @@ __global__ __launch_bounds__(FNT) void flatten_kernel(FlatArgs<S, R> a, int gx, 
 // STAGE 2: Uout = 0.5 Un + 0.5 (Uin + dt L(Uin)), Uout == Un allowed (each
 // cell reads Un only at itself).
 // ---------------------------------------------------------------------------
-template <class R>
-__device__ __forceinline__ void ppm_flat(const R* q, R chi, int recon, R& l, R& r) {
-  recon5<R>(q[0], q[1], q[2], q[3], q[4], recon, l, r);
-  l = chi * l + (R(1) - chi) * q[2];
-  r = chi * r + (R(1) - chi) * q[2];
+// Reconstruction of the five primitives of one cell, each blended toward the
+// cell average with the flattening coefficient ch: a = ch a + (1 - ch) q.
+// Where ch = 1 (away from shocks, most of the grid) the blend returns a
+// itself, so it is skipped, and whole waves with ch = 1 branch past it.
+// qat(v, q) fetches the five averages of variable v along the axis.
+template <class R, class Q>
+__device__ __forceinline__ void recon_flat5(const Q& qat, R ch, int recon, R* l, R* r) {
+  R c[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    R q[5];
+    qat(v, q);
+    recon5<R>(q[0], q[1], q[2], q[3], q[4], recon, l[v], r[v]);
+    c[v] = q[2];
+  }
+  if (ch != R(1)) {
+    const R om = R(1) - ch;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      l[v] = ch * l[v] + om * c[v];
+      r[v] = ch * r[v] + om * c[v];
+    }
+  }
 }
 
 // LDS of one stage tile.  SPLIT: x and y face states and fluxes have buffers
@@ -451,11 +469,12 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
   // (rho, w, u, v, P) so that it feeds the z Riemann problem directly
   auto recon_z = [&](R ch, R* L, R* Rr) {
     R l[5], r[5];
+    recon_flat5<R>(
+        [&](int v, R* q) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      R q[5] = {w[v][0], w[v][1], w[v][2], w[v][3], w[v][4]};
-      ppm_flat<R>(q, ch, a.recon, l[v], r[v]);
-    }
+          for (int s = 0; s < 5; ++s) q[s] = w[v][s];
+        },
+        ch, a.recon, l, r);
     L[0] = l[0]; L[1] = l[3]; L[2] = l[1]; L[3] = l[2]; L[4] = l[4];
     Rr[0] = r[0]; Rr[1] = r[3]; Rr[2] = r[1]; Rr[3] = r[2]; Rr[4] = r[4];
   };
@@ -524,11 +543,18 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
         const int xx = it % (TX + 2) - 1, yy = it / (TX + 2);
         if (xx <= tw && yy < th) {
           const R ch = sm.chiP[yy + 1][xx + 1];
+          R l[5], r[5];
+          recon_flat5<R>(
+              [&](int v, R* q) {
+                const R* row = &sm.Wp[v][yy + 3][xx + 1];
+#pragma unroll
+                for (int s = 0; s < 5; ++s) q[s] = row[s];
+              },
+              ch, a.recon, l, r);
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            const R* row = &sm.Wp[v][yy + 3][xx + 1];
-            R q[5] = {row[0], row[1], row[2], row[3], row[4]};
-            ppm_flat<R>(q, ch, a.recon, xL[v * XS + it], xR[v * XS + it]);
+            xL[v * XS + it] = l[v];
+            xR[v * XS + it] = r[v];
           }
         }
       }
@@ -560,11 +586,17 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
         const int xx = it % TX, yy = it / TX - 1;
         if (xx < tw && yy <= th) {
           const R ch = sm.chiP[yy + 1][xx + 1];
+          R l[5], r[5];
+          recon_flat5<R>(
+              [&](int v, R* q) {
+#pragma unroll
+                for (int s = 0; s < 5; ++s) q[s] = sm.Wp[v][yy + 1 + s][xx + 3];
+              },
+              ch, a.recon, l, r);
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            R q[5] = {sm.Wp[v][yy + 1][xx + 3], sm.Wp[v][yy + 2][xx + 3], sm.Wp[v][yy + 3][xx + 3],
-                      sm.Wp[v][yy + 4][xx + 3], sm.Wp[v][yy + 5][xx + 3]};
-            ppm_flat<R>(q, ch, a.recon, yL[v * YS + it], yR[v * YS + it]);
+            yL[v * YS + it] = l[v];
+            yR[v * YS + it] = r[v];
           }
         }
       }

@@ -32,6 +32,17 @@ template <class R> __device__ __forceinline__ R rmax(R a, R b) { return fmax(a, 
 // CW84 extremum test with a monotonized-central linear fallback, CW84
 // overshoot correction.  Written branch-free (selects) for SIMD execution.
 // ---------------------------------------------------------------------------
+// Half the monotonized-central slope, sign(dc) min(2|dr|, 2|dl|, |dc|/2) / 2
+// (0 at an extremum of the averages), taken as min(|dr|, |dl|, |dc|/4) with
+// the sign of dc: scaling by powers of two is exact, so the interface values
+// q0 -+ h carry the same bits as q0 -+ slope/2.  Where dr dl > 0 neither h
+// nor dc is zero, so copysign agrees with the sign test on dc.
+template <class R>
+__device__ __forceinline__ R mc_half_slope(R dl, R dr, R dc) {
+  const R h = copysign(rmin(rmin(fabs(dr), fabs(dl)), R(0.25) * fabs(dc)), dc);
+  return (dr * dl > R(0)) ? h : R(0);
+}
+
 template <class R>
 __device__ __forceinline__ void ppm(R qm2, R qm1, R q0, R qp1, R qp2, R& aL, R& aR) {
   const R c7 = R(7.0 / 12.0), c1 = R(1.0 / 12.0);
@@ -42,9 +53,7 @@ __device__ __forceinline__ void ppm(R qm2, R qm1, R q0, R qp1, R qp2, R& aL, R& 
   fl = rmin(rmax(fl, lo), hi);
   fr = rmin(rmax(fr, lo), hi);
   const R dl = q0 - qm1, dr = qp1 - q0, dc = qp1 - qm1;
-  R s = rmin(rmin(R(2) * fabs(dr), R(2) * fabs(dl)), R(0.5) * fabs(dc));
-  s = (dc < R(0)) ? -s : s;
-  s = (dr * dl > R(0)) ? s : R(0);
+  const R h = mc_half_slope(dl, dr, dc);
   const bool ext = (fr - q0) * (q0 - fl) <= R(0);
   const R del = fr - fl;
   const R a6 = R(6) * (q0 - R(0.5) * (fl + fr));
@@ -53,19 +62,17 @@ __device__ __forceinline__ void ppm(R qm2, R qm1, R q0, R qp1, R qp2, R& aL, R& 
   const bool ovr = !ovl && (da < -d2);
   const R fl2 = ovl ? R(3) * q0 - R(2) * fr : fl;
   const R fr2 = ovr ? R(3) * q0 - R(2) * fl : fr;
-  aL = ext ? q0 - R(0.5) * s : fl2;
-  aR = ext ? q0 + R(0.5) * s : fr2;
+  aL = ext ? q0 - h : fl2;
+  aR = ext ? q0 + h : fr2;
 }
 
 // PLM with the monotonized-central limiter (Section 2.2.1 alternative).
 template <class R>
 __device__ __forceinline__ void plm(R qm1, R q0, R qp1, R& aL, R& aR) {
   const R dl = q0 - qm1, dr = qp1 - q0, dc = qp1 - qm1;
-  R s = rmin(rmin(R(2) * fabs(dr), R(2) * fabs(dl)), R(0.5) * fabs(dc));
-  s = (dc < R(0)) ? -s : s;
-  s = (dr * dl > R(0)) ? s : R(0);
-  aL = q0 - R(0.5) * s;
-  aR = q0 + R(0.5) * s;
+  const R h = mc_half_slope(dl, dr, dc);
+  aL = q0 - h;
+  aR = q0 + h;
 }
 
 // Reconstruction selected at run time (uniform across the launch).
@@ -103,8 +110,6 @@ __device__ __forceinline__ void hllc(const R* WL, const R* WR, const GasK<R>& k,
   const R g = k.g;
   const R cL = sqrt(g * pL / rL);
   const R cR = sqrt(g * pR / rR);
-  const R EL = pL * k.inv_gm1 + R(0.5) * rL * (uL * uL + (vL * vL + wL * wL));
-  const R ER = pR * k.inv_gm1 + R(0.5) * rR * (uR * uR + (vR * vR + wR * wR));
   const R rbar = R(0.5) * (rL + rR);
   const R cbar = R(0.5) * (cL + cR);
   const R ps = rmax(R(0), R(0.5) * (pL + pR) - R(0.5) * (uR - uL) * rbar * cbar);
@@ -115,11 +120,12 @@ __device__ __forceinline__ void hllc(const R* WL, const R* WR, const GasK<R>& k,
   const R Ss = ((pR - pL) + rL * uL * (SL - uL) - rR * uR * (SR - uR)) / (rL * (SL - uL) - rR * (SR - uR));
   // Side and branch exactly as the four-way selection on (S_L, S*, S_R):
   // 0 <= S_L: left flux; else 0 <= S*: left star; else 0 < S_R: right star;
-  // else right flux.  Only the chosen side's fluxes are formed.
+  // else right flux.  Only the chosen side's energy and fluxes are formed.
   const bool left = (R(0) <= SL) || (R(0) <= Ss);
   const bool star = !(R(0) <= SL) && ((R(0) <= Ss) || (R(0) < SR));
   const R r = left ? rL : rR, u = left ? uL : uR, v = left ? vL : vR, w = left ? wL : wR;
-  const R p = left ? pL : pR, E = left ? EL : ER, S = left ? SL : SR;
+  const R p = left ? pL : pR, S = left ? SL : SR;
+  const R E = p * k.inv_gm1 + R(0.5) * r * (u * u + (v * v + w * w));
   const R f0 = r * u, f1 = r * u * u + p, f2 = r * u * v, f3 = r * u * w, f4 = u * (E + p);
   const R ph = (S - u) / (S - Ss);
   const R Us0 = ph * r, Us1 = ph * (r * Ss), Us2 = ph * (r * v), Us3 = ph * (r * w);
