@@ -14,6 +14,7 @@
 // pass through LDS so that every interface is reconstructed and solved once.
 #pragma once
 #include "qk_device.hpp"
+#include <type_traits>
 
 namespace qk {
 
@@ -466,15 +467,30 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
     }
   };
   // z reconstruction of the cell centred in the window; z-rotated output
-  // (rho, w, u, v, P) so that it feeds the z Riemann problem directly
-  auto recon_z = [&](R ch, R* L, R* Rr) {
+  // (rho, w, u, v, P) so that it feeds the z Riemann problem directly.  PPM
+  // keeps the unlimited upper interface value (fzr) for the next plane, whose
+  // lower interface it is (CARRY: the window has moved by one plane since).
+  R fzr[5];
+  auto recon_z = [&](R ch, R* L, R* Rr, auto carry) {
     R l[5], r[5];
-    recon_flat5<R>(
-        [&](int v, R* q) {
 #pragma unroll
-          for (int s = 0; s < 5; ++s) q[s] = w[v][s];
-        },
-        ch, a.recon, l, r);
+    for (int v = 0; v < 5; ++v) {
+      if (a.recon == 1) {
+        plm<R>(w[v][1], w[v][2], w[v][3], l[v], r[v]);
+      } else {
+        const R fl = decltype(carry)::value ? fzr[v] : ppm_iface<R>(w[v][0], w[v][1], w[v][2], w[v][3]);
+        fzr[v] = ppm_iface<R>(w[v][1], w[v][2], w[v][3], w[v][4]);
+        ppm_limit<R>(w[v][1], w[v][2], w[v][3], fl, fzr[v], l[v], r[v]);
+      }
+    }
+    if (ch != R(1)) {
+      const R om = R(1) - ch;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        l[v] = ch * l[v] + om * w[v][2];
+        r[v] = ch * r[v] + om * w[v][2];
+      }
+    }
     L[0] = l[0]; L[1] = l[3]; L[2] = l[1]; L[3] = l[2]; L[4] = l[4];
     Rr[0] = r[0]; Rr[1] = r[3]; Rr[2] = r[1]; Rr[3] = r[2]; Rr[4] = r[4];
   };
@@ -483,12 +499,12 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
 #pragma unroll
     for (int s = 0; s < 5; ++s) load_w(z0 - 3 + s, s);  // centred on z0-1
     R l[5], rprev[5];
-    recon_z(chi[cell(b, i, j, z0 - 1)], l, rprev);
+    recon_z(chi[cell(b, i, j, z0 - 1)], l, rprev, std::false_type{});
     shift_w();
     load_w(z0 + 2, 4);  // centred on z0
     R rcur[5];
     chk = chi[cell(b, i, j, z0)];
-    recon_z(chk, l, rcur);
+    recon_z(chk, l, rcur, std::true_type{});
     hllc<R>(rprev, l, g, Fz);
 #pragma unroll
     for (int v = 0; v < 5; ++v) aRz[v] = rcur[v];
@@ -663,7 +679,7 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
     if (act) {
       // ---- z sweep: cell k+1 is centred in the window
       R aLn[5], aRn[5], Fk[5];
-      recon_z(chn, aLn, aRn);
+      recon_z(chn, aLn, aRn, std::true_type{});
       hllc<R>(aRz, aLn, g, Fk);
       // un-rotate (rho, w, u, v, E) fluxes to (rho, x, y, z, E)
       R Fn[5] = {Fk[0], Fk[2], Fk[3], Fk[1], Fk[4]};

@@ -43,11 +43,17 @@ __device__ __forceinline__ R mc_half_slope(R dl, R dr, R dc) {
   return (dr * dl > R(0)) ? h : R(0);
 }
 
+// Fourth-order interface value between a and b from the averages a-1 = am,
+// a, b, b+1 = bp.  A cell's right value and its right neighbour's left value
+// are the same expression on the same operands, so a sweep may carry it.
 template <class R>
-__device__ __forceinline__ void ppm(R qm2, R qm1, R q0, R qp1, R qp2, R& aL, R& aR) {
-  const R c7 = R(7.0 / 12.0), c1 = R(1.0 / 12.0);
-  R fl = c7 * (qm1 + q0) - c1 * (qm2 + qp1);
-  R fr = c7 * (q0 + qp1) - c1 * (qm1 + qp2);
+__device__ __forceinline__ R ppm_iface(R am, R a, R b, R bp) {
+  return R(7.0 / 12.0) * (a + b) - R(1.0 / 12.0) * (am + bp);
+}
+
+// PPM limiting of one cell from its unlimited interface values fl, fr.
+template <class R>
+__device__ __forceinline__ void ppm_limit(R qm1, R q0, R qp1, R fl, R fr, R& aL, R& aR) {
   const R lo = rmin(qm1, rmin(q0, qp1));
   const R hi = rmax(qm1, rmax(q0, qp1));
   fl = rmin(rmax(fl, lo), hi);
@@ -64,6 +70,11 @@ __device__ __forceinline__ void ppm(R qm2, R qm1, R q0, R qp1, R qp2, R& aL, R& 
   const R fr2 = ovr ? R(3) * q0 - R(2) * fl : fr;
   aL = ext ? q0 - h : fl2;
   aR = ext ? q0 + h : fr2;
+}
+
+template <class R>
+__device__ __forceinline__ void ppm(R qm2, R qm1, R q0, R qp1, R qp2, R& aL, R& aR) {
+  ppm_limit<R>(qm1, q0, qp1, ppm_iface<R>(qm2, qm1, q0, qp1), ppm_iface<R>(qm1, q0, qp1, qp2), aL, aR);
 }
 
 // PLM with the monotonized-central limiter (Section 2.2.1 alternative).

@@ -305,9 +305,20 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
       for (int s = 0; s < 4; ++s) w[v][s] = w[v][s + 1];
     }
   };
-  auto recon_z = [&](R* L, R* Rr) {
+  // PPM keeps the unlimited upper interface value (fzr) for the next plane,
+  // whose lower interface it is (CARRY: the window has moved by one plane).
+  R fzr[4];
+  auto recon_z = [&](R* L, R* Rr, auto carry) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) recon5<R>(w[v][0], w[v][1], w[v][2], w[v][3], w[v][4], p.recon, L[v], Rr[v]);
+    for (int v = 0; v < 4; ++v) {
+      if (p.recon == 1) {
+        plm<R>(w[v][1], w[v][2], w[v][3], L[v], Rr[v]);
+      } else {
+        const R fl = decltype(carry)::value ? fzr[v] : ppm_iface<R>(w[v][0], w[v][1], w[v][2], w[v][3]);
+        fzr[v] = ppm_iface<R>(w[v][1], w[v][2], w[v][3], w[v][4]);
+        ppm_limit<R>(w[v][1], w[v][2], w[v][3], fl, fzr[v], L[v], Rr[v]);
+      }
+    }
   };
   auto rho_at = [&](int kk) { return R(Ug[cell(b, i, j, kk)]); };
 
@@ -317,13 +328,13 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
 #pragma unroll
     for (int s = 0; s < 5; ++s) load_w(z0 - 3 + s, s);
     R l[4], rprev[4];
-    recon_z(l, rprev);
+    recon_z(l, rprev, std::false_type{});
 #pragma unroll
     for (int v = 0; v < 4; ++v) cprev[v] = w[v][2];  // cell z0-1
     shift_w();
     load_w(z0 + 2, 4);
     R rcur[4], ccur[4];
-    recon_z(l, rcur);
+    recon_z(l, rcur, std::true_type{});
 #pragma unroll
     for (int v = 0; v < 4; ++v) ccur[v] = w[v][2];  // cell z0
     R rl = R(0), rr = R(0);
@@ -505,7 +516,7 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
       if (tauc) rz_k1 = rhn;
       // ---- z sweep: cell k+1 centred in the window
       R aLn[4], aRn[4], Fk[4], ck[4], ck1[4];
-      recon_z(aLn, aRn);
+      recon_z(aLn, aRn, std::true_type{});
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         ck[v] = w[v][1];

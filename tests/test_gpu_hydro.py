@@ -202,3 +202,19 @@ def test_negative_density_is_reported(ctx):
     ctx.hydro_step(b, Ud, qb.hydro_params(p["gamma"], p["cfl"]), dt=1e-4)
     assert ctx.sync_status() == qb.QK_ENEGATIVE
     assert ctx.sync_status() == qb.QK_OK
+
+
+def test_box_limits_are_rejected_before_any_launch(ctx):
+    """Degenerate and oversized boxes, and an empty batch, are refused on the
+    host.  The state pointers are NULL, so a missing check could not reach a
+    kernel either: each call must fail with the box's own message."""
+    hp = qb.hydro_params(1.4, 0.3)
+    cases = [((0, 8, 8), 4, "extent"), ((8, 8, 8), 3, "ng"), ((16384, 16384, 16384), 4, "too large")]
+    for n, ng, what in cases:
+        b = inputs.Box(n, ng, (1.0, 1.0, 1.0), ((0, 0), (0, 0), (0, 0)))
+        st = ctx.lib.quokka_hydro_step(ctx.h, qb.make_box(b), None, 0, hp, None, 1e-3, None, None)
+        assert st == qb.QK_EINVAL, (n, ng)
+        assert what in ctx.lib.quokka_last_error(ctx.h).decode(), (n, ng)
+    st = ctx.lib.quokka_batch_step(ctx.h, None, 0, None, None, 0, hp, None, None, None)
+    assert st == qb.QK_EINVAL
+    assert "empty" in ctx.lib.quokka_last_error(ctx.h).decode()
