@@ -68,9 +68,10 @@ __device__ __forceinline__ void rad_flux(R EL, R fLx, R fLy, R fLz, R nL, R ER, 
 
 // Face between cell "l" (reconstructed right state aL*) and cell "r": choose
 // the reconstructed states or, if either |f| exceeds 1, both cell averages,
-// then the optical-depth factor, then the flux.
-template <class R>
-__device__ __forceinline__ void rad_face(const R* sl, const R* sr, const R* cl, const R* cr, R rhol, R rhor, R dxd,
+// then the optical-depth factor, then the flux.  cells(cl, cr) fetches the
+// two cell averages; the fallback is rare, so whole waves skip the fetch.
+template <class R, class Cells>
+__device__ __forceinline__ void rad_face(const R* sl, const R* sr, const Cells& cells, R rhol, R rhor, R dxd,
                                          int d, const RadParamsDev& p, R c, R chat, R ratio, R cc, R* out) {
   R nl = sqrt((sl[1] * sl[1] + sl[2] * sl[2]) + sl[3] * sl[3]);
   R nr = sqrt((sr[1] * sr[1] + sr[2] * sr[2]) + sr[3] * sr[3]);
@@ -78,17 +79,21 @@ __device__ __forceinline__ void rad_face(const R* sl, const R* sr, const R* cl, 
   R L[4], Rr[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    L[v] = fb ? cl[v] : sl[v];
-    Rr[v] = fb ? cr[v] : sr[v];
+    L[v] = sl[v];
+    Rr[v] = sr[v];
   }
-  if (fb) {  // rare: whole waves skip the norms of the cell averages
-    nl = sqrt((cl[1] * cl[1] + cl[2] * cl[2]) + cl[3] * cl[3]);
-    nr = sqrt((cr[1] * cr[1] + cr[2] * cr[2]) + cr[3] * cr[3]);
+  if (fb) {
+    cells(L, Rr);
+    nl = sqrt((L[1] * L[1] + L[2] * L[2]) + L[3] * L[3]);
+    nr = sqrt((Rr[1] * Rr[1] + Rr[2] * Rr[2]) + Rr[3] * Rr[3]);
   }
   R eps = R(1);
   if (p.tau_correction) {
+    // min(1, 1/tau) is 1 unless tau > 1: waves with no optically thick face
+    // skip the division (a wave-uniform branch)
     const R tau = dxd * R(p.kappa_R) * (R(0.5) * (rhol + rhor));
-    eps = fb ? R(1) : rmin(R(1), R(1) / tau);
+    const bool thick = !fb && tau > R(1);
+    if (__ballot(thick)) eps = thick ? R(1) / tau : R(1);
   }
   rad_flux<R>(L[0], L[1], L[2], L[3], nl, Rr[0], Rr[1], Rr[2], Rr[3], nr, d, p.closure, c, chat, ratio, cc, eps, out);
 }
@@ -342,7 +347,16 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
       rl = rho_at(z0 - 1);
       rr = rho_at(z0);
     }
-    rad_face<R>(rprev, l, cprev, ccur, rl, rr, R(b.dx2), 2, p, c, chat, ratio, cc, Fz);
+    rad_face<R>(
+        rprev, l,
+        [&](R* cl, R* cr) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            cl[v] = cprev[v];
+            cr[v] = ccur[v];
+          }
+        },
+        rl, rr, R(b.dx2), 2, p, c, chat, ratio, cc, Fz);
 #pragma unroll
     for (int v = 0; v < 4; ++v) aRz[v] = rcur[v];
     rz_k1 = rr;
@@ -420,16 +434,23 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
         const int fx = it % (TX + 1), yy = it / (TX + 1);
         if (fx <= tw && yy < th) {
           const int il = yy * (TX + 2) + fx, ir = il + 1;
-          R sl[4], sr[4], cl[4], cr[4], F[4];
+          R sl[4], sr[4], F[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             sl[v] = xR[v * XS + il];
             sr[v] = xL[v * XS + ir];
-            cl[v] = Qp[v][yy + 3][fx + 2];
-            cr[v] = Qp[v][yy + 3][fx + 3];
           }
           const R rl = tauc ? rhoP[yy + 1][fx] : R(0), rr = tauc ? rhoP[yy + 1][fx + 1] : R(0);
-          rad_face<R>(sl, sr, cl, cr, rl, rr, R(b.dx0), 0, p, c, chat, ratio, cc, F);
+          rad_face<R>(
+              sl, sr,
+              [&](R* cl, R* cr) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                  cl[v] = Qp[v][yy + 3][fx + 2];
+                  cr[v] = Qp[v][yy + 3][fx + 3];
+                }
+              },
+              rl, rr, R(b.dx0), 0, p, c, chat, ratio, cc, F);
 #pragma unroll
           for (int v = 0; v < 4; ++v) xF[v * XFS + it] = F[v];
           if (REG && a.reg && (fx < tw || x0 + tw == b.n0)) {
@@ -455,16 +476,23 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
         const int xx = it % TX, fy = it / TX;
         if (xx < tw && fy <= th) {
           const int il = fy * TX + xx, ir = il + TX;
-          R sl[4], sr[4], cl[4], cr[4], F[4];
+          R sl[4], sr[4], F[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             sl[v] = yR[v * YS + il];
             sr[v] = yL[v * YS + ir];
-            cl[v] = Qp[v][fy + 2][xx + 3];
-            cr[v] = Qp[v][fy + 3][xx + 3];
           }
           const R rl = tauc ? rhoP[fy][xx + 1] : R(0), rr = tauc ? rhoP[fy + 1][xx + 1] : R(0);
-          rad_face<R>(sl, sr, cl, cr, rl, rr, R(b.dx1), 1, p, c, chat, ratio, cc, F);
+          rad_face<R>(
+              sl, sr,
+              [&](R* cl, R* cr) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                  cl[v] = Qp[v][fy + 2][xx + 3];
+                  cr[v] = Qp[v][fy + 3][xx + 3];
+                }
+              },
+              rl, rr, R(b.dx1), 1, p, c, chat, ratio, cc, F);
 #pragma unroll
           for (int v = 0; v < 4; ++v) yF[v * YFS + it] = F[v];
           if (REG && a.reg && (fy < th || y0 + th == b.n1)) {
@@ -515,14 +543,18 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
     if (act) {
       if (tauc) rz_k1 = rhn;
       // ---- z sweep: cell k+1 centred in the window
-      R aLn[4], aRn[4], Fk[4], ck[4], ck1[4];
+      R aLn[4], aRn[4], Fk[4];
       recon_z(aLn, aRn, std::true_type{});
+      rad_face<R>(
+          aRz, aLn,
+          [&](R* cl, R* cr) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        ck[v] = w[v][1];
-        ck1[v] = w[v][2];
-      }
-      rad_face<R>(aRz, aLn, ck, ck1, rz_k, rz_k1, R(b.dx2), 2, p, c, chat, ratio, cc, Fk);
+            for (int v = 0; v < 4; ++v) {
+              cl[v] = w[v][1];
+              cr[v] = w[v][2];
+            }
+          },
+          rz_k, rz_k1, R(b.dx2), 2, p, c, chat, ratio, cc, Fk);
       if (REG && a.reg) {  // face k+1
         const double Fd[4] = {double(Fk[0]), double(Fk[1]), double(Fk[2]), double(Fk[3])};
         reg_add<4>(a.reg, a.rlo, a.rhi, 2, k + 1, i, j, 0.5 * dt * a.rw, Fd);
