@@ -1,7 +1,7 @@
-"""Two-level (refinement ratio 2) step driver shared by the oracle and GPU
-level-synchronisation tests.  `A` supplies fill_ghosts, max_signal,
+"""Two-level (refinement ratio 2) step sequencing shared by the oracle and
+GPU level-synchronisation tests.  `A` supplies fill_ghosts, max_signal,
 hydro_step_reg, prolong, average_down and reflux with the oracle's
-signatures; the driver only sequences them (Section 2.2: coarse step, two
+signatures; this module only calls them in order (Section 2.2: coarse step, two
 fine steps with ghosts interpolated in space and time from the coarse level,
 average-down, reflux)."""
 import numpy as np
