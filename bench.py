@@ -236,15 +236,37 @@ def bench_batch(ctx, qb, inputs, torch, steps, dtype):
                         "one graph replay per level step"}
 
 
-def cpu_baseline_hydro(inputs, oracle):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_hydro(inputs, oracle, steps=3):
+    """The oracle on the host cores: `steps` FP64 hydro steps of the full 256^3
+    benchmark box on all threads, then one step on a single thread."""
     b, U, p = inputs.hydro_shock(n=256)
     threads = oracle.set_threads(0)
     oracle.fill_ghosts(b, U)
     t0 = time.perf_counter()
-    oracle.hydro_step(b, U, p["gamma"], p["cfl"])
+    for _ in range(steps):
+        oracle.hydro_step(b, U, p["gamma"], p["cfl"])
     t = time.perf_counter() - t0
-    return {"value": b.ncells / t, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": "one FP64 hydro step of the full 256^3 benchmark box (%.1f s)" % t}
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.hydro_step(b, U, p["gamma"], p["cfl"])
+    t1 = time.perf_counter() - t1
+    oracle.set_threads(0)
+    return {"value": steps * b.ncells / t, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": "%d FP64 hydro steps of the full 256^3 benchmark box on %d threads (%.1f s)" % (steps, threads, t),
+            "value_1_thread": b.ncells / t1,
+            "sample_1_thread": "one further step on 1 thread (%.1f s)" % t1,
+            "cpu_model": cpu_model()}
 
 
 def run_only(args, torch, qb, inputs):

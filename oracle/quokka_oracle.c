@@ -61,7 +61,10 @@ static inline size_t IX(const geo* g, int i, int j, int k) {
 
 int oracle_set_threads(int n) {
 #ifdef _OPENMP
-  if (n > 0) omp_set_num_threads(n);
+  /* n <= 0 restores the process default (OMP_NUM_THREADS, else all cores) */
+  static int dflt = 0;
+  if (dflt == 0) dflt = omp_get_max_threads();
+  omp_set_num_threads(n > 0 ? n : dflt);
   return omp_get_max_threads();
 #else
   (void)n;
