@@ -236,6 +236,15 @@ def bench_batch(ctx, qb, inputs, torch, steps, dtype):
                         "one graph replay per level step"}
 
 
+def environment(torch):
+    from paper_2110_01792_amd import build as pb
+    return {"device": torch.cuda.get_device_name(0), "hip": torch.version.hip, "torch": torch.__version__,
+            "library_flags": "hipcc --offload-arch=%s %s" % (pb.ARCH, " ".join(pb.FLAGS)),
+            "timing": "device synchronised, HIP events around the timed steps on the stream the library "
+                      "launches on, device synchronised; no host synchronisation inside (dt and N_sub stay on "
+                      "the device); per-kernel averages from the library's own HIP events in a second pass"}
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
@@ -395,6 +404,7 @@ def main():
         "rhd_mixed": r32,
         "batch_f64": b64,
         "batch_mixed": b32,
+        "environment": environment(torch),
     }
     if not args.no_cpu:
         import oracle

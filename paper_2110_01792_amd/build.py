@@ -23,10 +23,13 @@ def hipcc():
     return "hipcc"
 
 
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wall", "-Wno-unused-variable", "-Wno-unused-but-set-variable"]
+
+
 def build(verbose: bool = False, extra=()) -> str:
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wall", "-Wno-unused-variable", "-Wno-unused-but-set-variable",
+    cmd = [hipcc(), f"--offload-arch={ARCH}"] + FLAGS + [
            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            os.path.join(CSRC, "api.hip"), "-o", LIB + ".tmp"] + list(extra)
     if verbose:
