@@ -238,7 +238,9 @@ def bench_batch(ctx, qb, inputs, torch, steps, dtype):
 
 def environment(torch):
     from paper_2110_01792_amd import build as pb
-    return {"device": torch.cuda.get_device_name(0), "hip": torch.version.hip, "torch": torch.__version__,
+    props = torch.cuda.get_device_properties(0)
+    return {"device": torch.cuda.get_device_name(0), "arch": getattr(props, "gcnArchName", "unknown"),
+            "compute_units": props.multi_processor_count, "hip": torch.version.hip, "torch": torch.__version__,
             "library_flags": "hipcc --offload-arch=%s %s" % (pb.ARCH, " ".join(pb.FLAGS)),
             "timing": "device synchronised, HIP events around the timed steps on the stream the library "
                       "launches on, device synchronised; no host synchronisation inside (dt and N_sub stay on "
