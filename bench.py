@@ -118,15 +118,19 @@ RAD_BYTES_STAGE2 = 168.0   # read Ur1, Ur (64) + gas (40), write Ur (32) + m, E 
 RHD_BYTES_PER_CELL_STEP = HYDRO_BYTES_PER_CELL_STEP + 10 * (RAD_BYTES_STAGE1 + RAD_BYTES_STAGE2)
 
 
-def bench_rhd(ctx, qb, inputs, torch, steps, warmup, dtype, n=256, recon=0):
+def bench_rhd(ctx, qb, inputs, torch, steps, warmup, dtype, n=256, recon=0, closure=0, source=False):
     b, Ug, Ur, p = inputs.rhd_lognormal(n=n)
-    p = dict(p, recon=recon)
+    p = dict(p, recon=recon, closure=closure)
     G = torch.from_numpy(Ug).to(dtype).cuda()
     R = torch.from_numpy(Ur).to(dtype).cuda()
     del Ug, Ur
     ctx.fill_ghosts(b, G)
     ctx.fill_ghosts(b, R)
-    rp = qb.rad_params(p)
+    J = None
+    if source:  # seeded per-cell radiation source rate, uniform in [0, 200)
+        gen = torch.Generator(device="cpu").manual_seed(7)
+        J = (200.0 * torch.rand(tuple(b.shape), generator=gen, dtype=torch.float64)).to(dtype).cuda()
+    rp = qb.rad_params(p, source=J)
     step = lambda: ctx.rhd_step(b, G, R, rp)
     for _ in range(warmup):
         step()
@@ -146,11 +150,12 @@ def bench_rhd(ctx, qb, inputs, torch, steps, warmup, dtype, n=256, recon=0):
     out = {"ms_per_step": ms / steps, "cell_updates_per_s": ncell * steps / (ms * 1e-3), "status": int(st),
            "rad_stage1_ms_avg": r1_ms / max(n1, 1), "rad_stage2_couple_ms_avg": r2_ms / max(n2, 1),
            "hydro_stage_ms_avg": hs_ms / max(nh, 1), "launches": [n1, n2, nh], "newton_iter_max": it,
-           "ncells": ncell, "reconstruction": "PLM" if recon == 1 else "PPM"}
+           "ncells": ncell, "reconstruction": "PLM" if recon == 1 else "PPM",
+           "closure": ("Levermore", "Eddington", "Minerbo")[closure], "source": bool(source)}
     out["step_hbm_frac"] = RHD_BYTES_PER_CELL_STEP * scale * out["cell_updates_per_s"] / (HBM_PEAK_GBS * 1e9)
     out["rad_stage1_achieved_GBs"] = ncell * RAD_BYTES_STAGE1 * scale / (out["rad_stage1_ms_avg"] * 1e-3) / 1e9
     out["rad_stage2_achieved_GBs"] = ncell * RAD_BYTES_STAGE2 * scale / (out["rad_stage2_couple_ms_avg"] * 1e-3) / 1e9
-    del G, R
+    del G, R, J
     torch.cuda.empty_cache()
     return out
 
@@ -209,6 +214,63 @@ def mixed_error_rhd(ctx, qb, inputs, torch, nsteps=20):
             "rad_flux_l1_over_c_sum_Er": flux_vs_cE,
             "note": "each path takes its own CFL dt (both capped to N_sub,max dt_r, the same value); F starts "
                     "at zero and is bounded by c E_r, so its error is also given against c sum(E_r)"}
+
+
+def bench_amr(ctx, qb, inputs, torch, steps, warmup, n=256, m=256):
+    """Two levels, refinement ratio 2: a periodic n^3 coarse box and an m^3
+    fine box over its centre, smooth seeded field, dt held at its initial CFL
+    value.  One coarse step = ghost fill, coarse step with a flux register over
+    the footprint, two fine half steps with ghosts interpolated from the coarse
+    level in space and time, average-down, reflux.  Beside it, the same three
+    box steps without the AMR work (plain steps, fine ghosts held fixed)."""
+    off = ((n - m // 2) // 2,) * 3
+    cb, Uc, fb, Uf, off, hp_d = inputs.two_level(n=n, m=m, off=off, seed=61)
+    C = torch.from_numpy(Uc).cuda()
+    F = torch.from_numpy(Uf).cuda()
+    del Uc, Uf
+    hp = qb.hydro_params(hp_d["gamma"], hp_d["cfl"])
+    lo = tuple(off)
+    hi = tuple(off[d] + fb.n[d] // 2 for d in range(3))
+    ctx.fill_ghosts(cb, C)
+    ctx.prolong(cb, C, C, 0.0, fb, F, off)
+    dt = min(ctx.compute_dt(cb, C, hp=hp), 2.0 * ctx.compute_dt(fb, F, hp=hp))
+    C_old = torch.empty_like(C)
+    reg_c = torch.zeros(qb.region_size(lo, hi), dtype=torch.float64, device="cuda")
+    reg_f = torch.zeros(qb.region_size((0, 0, 0), fb.n), dtype=torch.float64, device="cuda")
+
+    def amr_step():
+        ctx.fill_ghosts(cb, C)
+        C_old.copy_(C)
+        reg_c.zero_()
+        reg_f.zero_()
+        ctx.hydro_step_reg(cb, C, hp, lo, hi, reg_c, dt=dt)
+        for alpha in (0.0, 0.5):
+            ctx.prolong(cb, C_old, C, alpha, fb, F, off)
+            ctx.hydro_step_reg(fb, F, hp, (0, 0, 0), fb.n, reg_f, dt=0.5 * dt)
+        ctx.average_down(fb, F, cb, C, off)
+        ctx.reflux(cb, C, lo, hi, reg_c, fb, reg_f)
+
+    def plain_steps():
+        ctx.hydro_step(cb, C, hp, dt=dt)
+        for _ in range(2):
+            ctx.hydro_step(fb, F, hp, dt=0.5 * dt)
+
+    for _ in range(warmup):
+        amr_step()
+    ms = timed_steps(amr_step, steps, torch)
+    st = ctx.sync_status()
+    ms_plain = timed_steps(plain_steps, steps, torch)
+    st = st or ctx.sync_status()
+    updates = cb.ncells + 2 * fb.ncells
+    out = {"ms_per_coarse_step": ms / steps, "cell_updates_per_s": updates * steps / (ms * 1e-3),
+           "status": int(st), "coarse_cells": cb.ncells, "fine_cells": fb.ncells,
+           "plain_ms_same_box_steps": ms_plain / steps, "amr_overhead": ms / ms_plain - 1.0,
+           "workload": "hydro FP64, periodic %d^3 coarse box, %d^3 fine box (ratio 2) over coarse cells "
+                       "[%d, %d)^3, smooth seeded field (gamma 5/3), dt fixed at its initial CFL 0.3 value; "
+                       "updates = coarse cells + 2 x fine cells per coarse step" % (n, m, lo[0], hi[0])}
+    del C, F, C_old
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_batch(ctx, qb, inputs, torch, steps, dtype):
@@ -302,6 +364,12 @@ def run_only(args, torch, qb, inputs):
         out = bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, f64 if args.only == "rhd" else f32)
     elif args.only == "rhdplm":
         out = bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, f64, recon=1)
+    elif args.only == "rhdvar":
+        out = {"eddington": bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, f64, closure=1),
+               "minerbo": bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, f64, closure=2),
+               "source": bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, f64, source=True)}
+    elif args.only == "amr":
+        out = bench_amr(ctx, qb, inputs, torch, args.steps, args.warmup)
     else:
         out = bench_batch(ctx, qb, inputs, torch, args.steps, f64)
     ctx.close()
@@ -314,7 +382,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--only", default="all", choices=["all", "hydro", "rhd", "hydro32", "rhd32", "sedov", "rhdplm", "batch", "copy"],
+    ap.add_argument("--only", default="all", choices=["all", "hydro", "rhd", "hydro32", "rhd32", "sedov", "rhdplm", "rhdvar", "amr", "batch", "copy"],
                     help="run one section only (for profiler runs); 'copy' runs a plain 2 GiB device copy used "
                          "to calibrate the HBM byte counters")
     args = ap.parse_args()
@@ -342,6 +410,14 @@ def main():
     plm64 = bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float64,
                       recon=1)
     log("Sedov:", sed64, "RHD PLM:", plm64)
+    log("closures, source term, two-level AMR ...")
+    variants = {
+        "rhd_eddington_f64": bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float64, closure=1),
+        "rhd_minerbo_f64": bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float64, closure=2),
+        "rhd_source_f64": bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float64, source=True),
+        "amr_two_level_f64": bench_amr(ctx, qb, inputs, torch, args.steps, args.warmup),
+    }
+    log("variants:", variants)
     log("mixed ...")
     h32, _, _ = bench_hydro(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float32)
     r32 = bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, torch.float32)
@@ -402,6 +478,7 @@ def main():
                                 paper_context="22.55 Mzones/s V100, 39.04 Mzones/s A100 (PLM, radiation-driven "
                                               "shell 256^3, 10 substeps)"),
         },
+        "variants": variants,
         "hydro_mixed": h32,
         "rhd_mixed": r32,
         "batch_f64": b64,

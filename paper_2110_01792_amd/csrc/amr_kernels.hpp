@@ -36,15 +36,22 @@ template <class S>
 __global__ __launch_bounds__(256) void prolong_kernel(const S* __restrict__ U0, const S* __restrict__ U1, double alpha,
                                                       DevBox cb, S* __restrict__ Uf, DevBox fb, int o0, int o1, int o2,
                                                       int nvar, int interior) {
+  // index range per variable: the whole ghosted box, or its ghost shell only
   const int ng = fb.ng;
   const int NX = fb.n0 + 2 * ng, NY = fb.n1 + 2 * ng, NZ = fb.n2 + 2 * ng;
-  const int64_t total = (int64_t)NX * NY * NZ * nvar;
+  const int64_t per_v = interior ? (int64_t)NX * NY * NZ : ghost_count(fb);
+  const int64_t total = per_v * nvar;
   for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < total; c += (int64_t)gridDim.x * 256) {
-    const int i = (int)(c % NX) - ng, j = (int)((c / NX) % NY) - ng;
-    const int k = (int)((c / ((int64_t)NX * NY)) % NZ) - ng;
-    const int v = (int)(c / ((int64_t)NX * NY * NZ));
-    const bool in = i >= 0 && i < fb.n0 && j >= 0 && j < fb.n1 && k >= 0 && k < fb.n2;
-    if (in && !interior) continue;
+    const int v = (int)(c / per_v);
+    const int64_t r = c - (int64_t)v * per_v;
+    int i, j, k;
+    if (interior) {
+      i = (int)(r % NX) - ng;
+      j = (int)((r / NX) % NY) - ng;
+      k = (int)(r / ((int64_t)NX * NY)) - ng;
+    } else {
+      ghost_cell(fb, r, i, j, k);
+    }
     const int P[3] = {o0 + floor_div2(i), o1 + floor_div2(j), o2 + floor_div2(k)};
     const int f[3] = {i, j, k};
     const S* a0 = U0 + (int64_t)v * cb.vs;

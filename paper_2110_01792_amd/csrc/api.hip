@@ -237,7 +237,7 @@ void launch_ghosts(const HostBox& hb, S* U, int nvar, hipStream_t s) {
 template <class S>
 void launch_ghost_copy(const HostBox& hb, S* dst, const S* src, int nvar, hipStream_t s) {
   const DevBox& d = hb.d;
-  const int64_t total = (int64_t)(d.n0 + 2 * d.ng) * (d.n1 + 2 * d.ng) * (d.n2 + 2 * d.ng);
+  const int64_t total = ghost_count(d);
   hipLaunchKernelGGL(ghost_copy_kernel<S>, dim3(grid_for(total, 256, 8192)), dim3(256), 0, s, dst, src, d, nvar);
 }
 

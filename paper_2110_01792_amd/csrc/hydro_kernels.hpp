@@ -813,34 +813,45 @@ __device__ __forceinline__ int map_index(int i, int n, int lo, int hi) {
   return i;
 }
 
-template <class S>
-__device__ __forceinline__ void ghost_body(S* __restrict__ U, const DevBox& b, const GhostBC& bc, int nvar) {
+// The ghost shell of a box as one index range [0, ghost_count): the two z
+// slabs (all x and y), then the two y slabs (interior z), then the two x
+// slabs (interior y and z); ghost_cell decodes an index into (i, j, k).
+__host__ __device__ __forceinline__ int64_t ghost_count(const DevBox& b) {
+  const int64_t NX = b.n0 + 2 * b.ng, NY = b.n1 + 2 * b.ng;
+  return 2 * b.ng * (NY * NX + (int64_t)b.n2 * NX + (int64_t)b.n2 * b.n1);
+}
+
+__device__ __forceinline__ void ghost_cell(const DevBox& b, int64_t c, int& i, int& j, int& k) {
   const int ng = b.ng;
   const int NX = b.n0 + 2 * ng, NY = b.n1 + 2 * ng;
   const int64_t nz_slab = (int64_t)2 * ng * NY * NX;
   const int64_t ny_slab = (int64_t)2 * ng * b.n2 * NX;
-  const int64_t nx_slab = (int64_t)2 * ng * b.n2 * b.n1;
-  const int64_t total = nz_slab + ny_slab + nx_slab;
+  if (c < nz_slab) {
+    i = (int)(c % NX) - ng;
+    j = (int)((c / NX) % NY) - ng;
+    const int kk = (int)(c / ((int64_t)NX * NY));
+    k = kk < ng ? kk - ng : b.n2 + (kk - ng);
+  } else if (c < nz_slab + ny_slab) {
+    const int64_t r = c - nz_slab;
+    i = (int)(r % NX) - ng;
+    const int jj = (int)((r / NX) % (2 * ng));
+    k = (int)(r / ((int64_t)NX * 2 * ng));
+    j = jj < ng ? jj - ng : b.n1 + (jj - ng);
+  } else {
+    const int64_t r = c - nz_slab - ny_slab;
+    const int ii = (int)(r % (2 * ng));
+    j = (int)((r / (2 * ng)) % b.n1);
+    k = (int)(r / ((int64_t)2 * ng * b.n1));
+    i = ii < ng ? ii - ng : b.n0 + (ii - ng);
+  }
+}
+
+template <class S>
+__device__ __forceinline__ void ghost_body(S* __restrict__ U, const DevBox& b, const GhostBC& bc, int nvar) {
+  const int64_t total = ghost_count(b);
   for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < total; c += (int64_t)gridDim.x * 256) {
     int i, j, k;
-    if (c < nz_slab) {
-      i = (int)(c % NX) - ng;
-      j = (int)((c / NX) % NY) - ng;
-      const int kk = (int)(c / ((int64_t)NX * NY));
-      k = kk < ng ? kk - ng : b.n2 + (kk - ng);
-    } else if (c < nz_slab + ny_slab) {
-      const int64_t r = c - nz_slab;
-      i = (int)(r % NX) - ng;
-      const int jj = (int)((r / NX) % (2 * ng));
-      k = (int)(r / ((int64_t)NX * 2 * ng));
-      j = jj < ng ? jj - ng : b.n1 + (jj - ng);
-    } else {
-      const int64_t r = c - nz_slab - ny_slab;
-      const int ii = (int)(r % (2 * ng));
-      j = (int)((r / (2 * ng)) % b.n1);
-      k = (int)(r / ((int64_t)2 * ng * b.n1));
-      i = ii < ng ? ii - ng : b.n0 + (ii - ng);
-    }
+    ghost_cell(b, c, i, j, k);
     // The x, y, z sequential fill writes a ghost cell in the fill of the last
     // axis (in x, y, z order) along which it lies outside; a fixed face there
     // leaves it as it is.  Its value comes from the cell mapped along that
@@ -876,14 +887,10 @@ __global__ __launch_bounds__(256) void ghost_kernel(S* __restrict__ U, DevBox b,
 template <class S>
 __global__ __launch_bounds__(256) void ghost_copy_kernel(S* __restrict__ dst, const S* __restrict__ src, DevBox b,
                                                          int nvar) {
-  const int ng = b.ng;
-  const int NX = b.n0 + 2 * ng, NY = b.n1 + 2 * ng, NZ = b.n2 + 2 * ng;
-  const int64_t total = (int64_t)NX * NY * NZ;
+  const int64_t total = ghost_count(b);
   for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < total; c += (int64_t)gridDim.x * 256) {
-    const int i = (int)(c % NX) - ng;
-    const int j = (int)((c / NX) % NY) - ng;
-    const int k = (int)(c / ((int64_t)NX * NY)) - ng;
-    if (i >= 0 && i < b.n0 && j >= 0 && j < b.n1 && k >= 0 && k < b.n2) continue;
+    int i, j, k;
+    ghost_cell(b, c, i, j, k);
     const int64_t o = cell(b, i, j, k);
     for (int v = 0; v < nvar; ++v) dst[o + v * b.vs] = src[o + v * b.vs];
   }
