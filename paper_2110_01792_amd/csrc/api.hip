@@ -334,10 +334,11 @@ void launch_stage(const HostBox& hb, const S* Uin, const S* Un, S* Uout, const R
     a.rhi[q] = rec ? rec->hi[q] : 0;
   }
   a.rw = rec ? rec->w : 0.0;
-  if (rec)
-    hipLaunchKernelGGL((stage_kernel<S, R, STAGE, true>), dim3(L.gx * L.gy * L.gz), dim3(SNT), 0, s, a);
-  else
-    hipLaunchKernelGGL((stage_kernel<S, R, STAGE, false>), dim3(L.gx * L.gy * L.gz), dim3(SNT), 0, s, a);
+  hipLaunchKernelGGL((stage_kernel<S, R, STAGE>), dim3(L.gx * L.gy * L.gz), dim3(SNT), 0, s, a);
+  if (rec) {
+    const int64_t nf = region_face_count(rec->lo, rec->hi);
+    hipLaunchKernelGGL((region_flux_kernel<S, R>), dim3(grid_for(nf, 256, 4096)), dim3(256), 0, s, a);
+  }
 }
 
 template <class S>

@@ -36,9 +36,9 @@ struct StageArgs {
   int recon;             // 0 PPM, 1 PLM
   unsigned long long* smax;  // stage 2: max(|v| + c_s) of the new state (ordered bits), or NULL
   uint32_t* err;
-  double* reg;           // flux register over the faces bounding region [rlo, rhi), or NULL
-  int rlo[3], rhi[3];
-  double rw;             // register weight: each face adds rw * dt/2 * F
+  double* reg;           // region_flux_kernel: flux register over the faces bounding
+  int rlo[3], rhi[3];    //   region [rlo, rhi) (the stage kernel ignores these)
+  double rw;             //   register weight: each face adds rw * dt/2 * F
 };
 
 // Flux-register slot of variable v (of nv) on face `side` (0 low, 1 high) of
@@ -52,19 +52,6 @@ __device__ __forceinline__ int64_t reg_slot(const int* lo, const int* hi, int d,
   if (d == 0) return ((int64_t)(v * 2 + side) * m2 + a) * m1 + b;
   if (d == 1) return nv * nx + ((int64_t)(v * 2 + side) * m2 + a) * m0 + b;
   return nv * (nx + ny) + ((int64_t)(v * 2 + side) * m1 + a) * m0 + b;
-}
-
-// Add w * F (unrotated, NV variables) at face `f` of axis d (between cells
-// f-1 and f) of cell row (p, q) = the other two cell indices in increasing
-// axis order, if that face lies on the region's boundary.
-template <int NV>
-__device__ __forceinline__ void reg_add(double* reg, const int* lo, const int* hi, int d, int f, int p, int q,
-                                        double w, const double* F) {
-  const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
-  if ((f != lo[d] && f != hi[d]) || p < lo[d1] || p >= hi[d1] || q < lo[d2] || q >= hi[d2]) return;
-  const int side = f == hi[d] ? 1 : 0;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) reg[reg_slot(lo, hi, d, v, side, q - lo[d2], p - lo[d1], NV)] += w * F[v];
 }
 
 // 1-D launch: consecutive hardware blocks are dealt round-robin to the 8
@@ -372,9 +359,8 @@ struct HydroSmem {
 
 // One tile of columns of one box: returns the thread's max(|v| + c_s) of the
 // new state (stage 2 with a.smax set), sets `bad` on a non-positive state.
-// NT threads (NT >= TX*TY); thread t owns column (t % TX, t / TX).  REG:
-// compiled with the flux-register recording (a.reg), else without it.
-template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE, bool REG = false>
+// NT threads (NT >= TX*TY); thread t owns column (t % TX, t / TX).
+template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE>
 __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, int tby, int tbz,
                                              HydroSmem<R, TX, TY, SPLIT>& sm, bool& bad_out) {
   using SM = HydroSmem<R, TX, TY, SPLIT>;
@@ -509,10 +495,6 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
 #pragma unroll
     for (int v = 0; v < 5; ++v) aRz[v] = rcur[v];
     load_cons(src_at(Uin, a.Ugh, b, i, j, z0 + 3), vs, cell(b, i, j, z0 + 3), cq);
-    if (REG && a.reg && z0 == 0) {  // face 0 belongs to the chunk starting at 0
-      const double F0[5] = {double(Fz[0]), double(Fz[2]), double(Fz[3]), double(Fz[1]), double(Fz[4])};
-      reg_add<5>(a.reg, a.rlo, a.rhi, 2, 0, i, j, 0.5 * dt * a.rw, F0);
-    }
   }
 #pragma unroll
   for (int m = 0; m < HPT; ++m) load_halo<5>(hc[m], hc[m].src, chi, (int64_t)z0 * pz, vs, hq[m]);
@@ -590,10 +572,6 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
 #pragma unroll
           for (int v = 0; v < 5; ++v) xF[v * XFS + it] = F[v];
           // a face on a tile edge belongs to the tile on its high side, except the box's last face
-          if (REG && a.reg && (fx < tw || x0 + tw == b.n0)) {
-            const double Fd[5] = {double(F[0]), double(F[1]), double(F[2]), double(F[3]), double(F[4])};
-            reg_add<5>(a.reg, a.rlo, a.rhi, 0, x0 + fx, y0 + yy, k, 0.5 * dt * a.rw, Fd);
-          }
         }
       }
     };
@@ -631,10 +609,6 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
           yF[2 * YFS + it] = F[1];
           yF[3 * YFS + it] = F[3];
           yF[4 * YFS + it] = F[4];
-          if (REG && a.reg && (fy < th || y0 + th == b.n1)) {
-            const double Fd[5] = {double(F[0]), double(F[2]), double(F[1]), double(F[3]), double(F[4])};
-            reg_add<5>(a.reg, a.rlo, a.rhi, 1, y0 + fy, x0 + xx, k, 0.5 * dt * a.rw, Fd);
-          }
         }
       }
     };
@@ -684,10 +658,6 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
       // un-rotate (rho, w, u, v, E) fluxes to (rho, x, y, z, E)
       R Fn[5] = {Fk[0], Fk[2], Fk[3], Fk[1], Fk[4]};
       R Fo[5] = {Fz[0], Fz[2], Fz[3], Fz[1], Fz[4]};
-      if (REG && a.reg) {  // face k+1
-        const double Fd[5] = {double(Fn[0]), double(Fn[1]), double(Fn[2]), double(Fn[3]), double(Fn[4])};
-        reg_add<5>(a.reg, a.rlo, a.rhi, 2, k + 1, i, j, 0.5 * dt * a.rw, Fd);
-      }
       const int64_t o = cell(b, i, j, k);
       double unew[5];
 #pragma unroll
@@ -727,19 +697,108 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
   return smax;
 }
 
+// Faces bounding region [lo, hi) as one index range: x faces (low side, then
+// high side), then y faces, then z faces; within an axis-d side, (a, b) are
+// the in-plane cell indices relative to the region (a along the slower of
+// the two other axes), as in reg_slot.
+struct RegionFace {
+  int d, side, a, b;
+};
+
+__host__ __device__ __forceinline__ int64_t region_face_count(const int* lo, const int* hi) {
+  const int64_t m0 = hi[0] - lo[0], m1 = hi[1] - lo[1], m2 = hi[2] - lo[2];
+  return 2 * (m1 * m2 + m0 * m2 + m0 * m1);
+}
+
+__device__ __forceinline__ RegionFace region_face(const int* lo, const int* hi, int64_t c) {
+  const int64_t m0 = hi[0] - lo[0], m1 = hi[1] - lo[1], m2 = hi[2] - lo[2];
+  const int64_t nface[3] = {m1 * m2, m0 * m2, m0 * m1};
+  RegionFace f;
+  f.d = 0;
+  while (c >= 2 * nface[f.d]) {
+    c -= 2 * nface[f.d];
+    ++f.d;
+  }
+  f.side = (int)(c / nface[f.d]);
+  const int64_t e = c % nface[f.d];
+  const int64_t mb = f.d == 0 ? m1 : m0;
+  f.a = (int)(e / mb);
+  f.b = (int)(e % mb);
+  return f;
+}
+
+// Flux register of one hydro stage: the fluxes at the faces bounding region
+// [rlo, rhi), recomputed from the stage input and its flattening
+// coefficients with the stage kernel's own device functions on the same
+// operands (conversion, reconstruction with flattening, HLLC, the same
+// rotations), so every face carries the bits the stage used; each adds
+// rw * dt/2 * F to its slot.  One thread per face.  Launched after the stage,
+// which leaves its input and chi as they were.
+template <class S, class R>
+__global__ __launch_bounds__(256) void region_flux_kernel(StageArgs<S, R> a) {
+  const DevBox& b = a.b;
+  const int lo[3] = {a.rlo[0], a.rlo[1], a.rlo[2]}, hi[3] = {a.rhi[0], a.rhi[1], a.rhi[2]};
+  const int64_t total = region_face_count(lo, hi);
+  const double dt = a.dt_ptr ? *a.dt_ptr : a.dt_val;
+  const double w = 0.5 * dt * a.rw;
+  const double gm1 = a.gamma - 1.0;
+  const GasK<R> g = gas_k<R>(a.gamma);
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < total; c += (int64_t)gridDim.x * 256) {
+    const RegionFace rf = region_face(lo, hi, c);
+    const int d = rf.d;
+    // cell f along d (the face lies between cells f-1 and f); unit step e along d
+    const int ei = d == 0, ej = d == 1, ek = d == 2;
+    const int i = d == 0 ? (rf.side ? hi[0] : lo[0]) : lo[0] + rf.b;
+    const int j = d == 1 ? (rf.side ? hi[1] : lo[1]) : (d == 0 ? lo[1] + rf.b : lo[1] + rf.a);
+    const int k = d == 2 ? (rf.side ? hi[2] : lo[2]) : lo[2] + rf.a;
+    R W[6][5];  // primitives of cells f-3 .. f+2 along d
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int ii = i + ei * (s - 3), jj = j + ej * (s - 3), kk = k + ek * (s - 3);
+      double q[5];
+      load_cons(src_at(a.Uin, a.Ugh, b, ii, jj, kk), b.vs, cell(b, ii, jj, kk), q);
+      bool dummy = false;
+      cons_to_prim<R>(q[0], q[1], q[2], q[3], q[4], gm1, W[s], dummy);
+    }
+    const R chl = a.chi[cell(b, i - ei, j - ej, k - ek)], chr = a.chi[cell(b, i, j, k)];
+    R ll[5], rl[5], lr[5], rr[5];
+    recon_flat5<R>(
+        [&](int v, R* q) {
+#pragma unroll
+          for (int s = 0; s < 5; ++s) q[s] = W[s][v];
+        },
+        chl, a.recon, ll, rl);  // cell f-1
+    recon_flat5<R>(
+        [&](int v, R* q) {
+#pragma unroll
+          for (int s = 0; s < 5; ++s) q[s] = W[s + 1][v];
+        },
+        chr, a.recon, lr, rr);  // cell f
+    // normal velocity first, as the sweeps order them: x (u, v, w), y (v, u, w), z (w, u, v)
+    const R WL[5] = {rl[0], d == 0 ? rl[1] : (d == 1 ? rl[2] : rl[3]), d == 0 ? rl[2] : rl[1],
+                     d == 2 ? rl[2] : rl[3], rl[4]};
+    const R WR[5] = {lr[0], d == 0 ? lr[1] : (d == 1 ? lr[2] : lr[3]), d == 0 ? lr[2] : lr[1],
+                     d == 2 ? lr[2] : lr[3], lr[4]};
+    R F[5];
+    hllc<R>(WL, WR, g, F);
+    const double Fd[5] = {double(F[0]), double(d == 0 ? F[1] : F[2]), double(d == 0 ? F[2] : (d == 1 ? F[1] : F[3])),
+                          double(d == 2 ? F[1] : F[3]), double(F[4])};
+#pragma unroll
+    for (int v = 0; v < 5; ++v) a.reg[reg_slot(lo, hi, d, v, rf.side, rf.a, rf.b, 5)] += w * Fd[v];
+  }
+}
+
 // Single-box stage: 16 x 14 tiles on 256 threads, so that each sweep phase
 // (18 x 14 and 16 x 16 reconstructions, 17 x 14 and 16 x 15 faces) is one
 // item per thread.
 constexpr int STX = 16, STY = 14, SNT = 256;
 
-// The recording variant is held to two blocks per CU (it would otherwise
-// take more than 256 registers and halve the occupancy).
-template <class S, class R, int STAGE, bool REG = false>
-__global__ __launch_bounds__(SNT, REG ? 2 : 1) void stage_kernel(StageArgs<S, R> a) {
+template <class S, class R, int STAGE>
+__global__ __launch_bounds__(SNT) void stage_kernel(StageArgs<S, R> a) {
   __shared__ HydroSmem<R, STX, STY, true> sm;
   const TileId tl = tile_of_block(a.gx, a.gy);
   bool bad = false;
-  const double smax = stage_tile<S, R, STX, STY, SNT, true, STAGE, REG>(a, tl.bx, tl.by, tl.bz, sm, bad);
+  const double smax = stage_tile<S, R, STX, STY, SNT, true, STAGE>(a, tl.bx, tl.by, tl.bz, sm, bad);
   if (bad) atomicOr(a.err, ERR_NEG);
   if (STAGE == 2 && a.smax) block_max_to<SNT>(smax, a.smax);
 }

@@ -38,9 +38,9 @@ struct RadStageArgs {
   int zc, gx, gy;
   uint32_t* err;
   uint32_t* iter_max;
-  double* reg;             // flux register over the faces bounding [rlo, rhi), or NULL
-  int rlo[3], rhi[3];
-  double rw;               // register weight: each face adds rw * dt_sub/2 * F
+  double* reg;             // rad_region_flux_kernel: flux register over the faces
+  int rlo[3], rhi[3];      //   bounding [rlo, rhi) (the stage kernel ignores these)
+  double rw;               //   register weight: each face adds rw * dt_sub/2 * F
 };
 
 // HLL flux of (E, F) along axis d between face states (E, f), |f| = nL, nR
@@ -200,9 +200,8 @@ struct RadSmem {
 
 // One tile of columns of one box for substep `a.sub` (the caller has checked
 // that the substep is active).  Returns the largest exchange iteration count.
-// NT threads (NT >= TX*TY); thread t owns column (t % TX, t / TX).  REG:
-// compiled with the flux-register recording (a.reg).
-template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE, bool REG = false>
+// NT threads (NT >= TX*TY); thread t owns column (t % TX, t / TX).
+template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE>
 __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tbx, int tby, int tbz, int N,
                                              RadSmem<R, TX, TY, SPLIT>& sm, bool& bad_out, bool& nfail_out) {
   using SM = RadSmem<R, TX, TY, SPLIT>;
@@ -360,10 +359,6 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
 #pragma unroll
     for (int v = 0; v < 4; ++v) aRz[v] = rcur[v];
     rz_k1 = rr;
-    if (REG && a.reg && z0 == 0) {  // face 0 belongs to the chunk starting at 0
-      const double F0[4] = {double(Fz[0]), double(Fz[1]), double(Fz[2]), double(Fz[3])};
-      reg_add<4>(a.reg, a.rlo, a.rhi, 2, 0, i, j, 0.5 * dt * a.rw, F0);
-    }
     load4(src_at(Uin, a.Ugh, b, i, j, z0 + 3), cell(b, i, j, z0 + 3), cq);
   }
 #pragma unroll
@@ -453,10 +448,6 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
               rl, rr, R(b.dx0), 0, p, c, chat, ratio, cc, F);
 #pragma unroll
           for (int v = 0; v < 4; ++v) xF[v * XFS + it] = F[v];
-          if (REG && a.reg && (fx < tw || x0 + tw == b.n0)) {
-            const double Fd[4] = {double(F[0]), double(F[1]), double(F[2]), double(F[3])};
-            reg_add<4>(a.reg, a.rlo, a.rhi, 0, x0 + fx, y0 + yy, k, 0.5 * dt * a.rw, Fd);
-          }
         }
       }
     };
@@ -495,10 +486,6 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
               rl, rr, R(b.dx1), 1, p, c, chat, ratio, cc, F);
 #pragma unroll
           for (int v = 0; v < 4; ++v) yF[v * YFS + it] = F[v];
-          if (REG && a.reg && (fy < th || y0 + th == b.n1)) {
-            const double Fd[4] = {double(F[0]), double(F[1]), double(F[2]), double(F[3])};
-            reg_add<4>(a.reg, a.rlo, a.rhi, 1, y0 + fy, x0 + xx, k, 0.5 * dt * a.rw, Fd);
-          }
         }
       }
     };
@@ -555,10 +542,6 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
             }
           },
           rz_k, rz_k1, R(b.dx2), 2, p, c, chat, ratio, cc, Fk);
-      if (REG && a.reg) {  // face k+1
-        const double Fd[4] = {double(Fk[0]), double(Fk[1]), double(Fk[2]), double(Fk[3])};
-        reg_add<4>(a.reg, a.rlo, a.rhi, 2, k + 1, i, j, 0.5 * dt * a.rw, Fd);
-      }
       const int64_t o = cell(b, i, j, k);
       double un[4];
 #pragma unroll
@@ -587,19 +570,85 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
   return itmax;
 }
 
-template <class S, class R, int STAGE, bool REG = false>
+template <class S, class R, int STAGE>
 __global__ __launch_bounds__(SNT, 2) void rad_stage_kernel(RadStageArgs<S, R> a) {
   const int N = a.nsub_ptr ? *a.nsub_ptr : a.nsub_val;
   if (a.sub >= N) return;  // block-uniform: the whole grid skips unused substeps
   __shared__ RadSmem<R, STX, STY, true> sm;
   const TileId tl = tile_of_block(a.gx, a.gy);
   bool bad = false, nfail = false;
-  const uint32_t itmax = rad_tile<S, R, STX, STY, SNT, true, STAGE, REG>(a, tl.bx, tl.by, tl.bz, N, sm, bad, nfail);
+  const uint32_t itmax = rad_tile<S, R, STX, STY, SNT, true, STAGE>(a, tl.bx, tl.by, tl.bz, N, sm, bad, nfail);
   if (bad) atomicOr(a.err, ERR_NEG);
   if (nfail) atomicOr(a.err, ERR_NEWTON);
   if (STAGE == 2) block_umax_to<SNT>(itmax, a.iter_max);
 }
 
+
+// Flux register of one radiation stage: the fluxes at the faces bounding
+// region [rlo, rhi), recomputed from the stage input (and the gas density
+// for the optical-depth factor) with the stage kernel's own device functions
+// on the same operands, so every face carries the bits the stage used; each
+// adds rw * dt_sub/2 * F to its slot.  One thread per face; guarded by the
+// device substep count like the stage.  Launched after the stage, which
+// leaves its input and the density as they were.
+template <class S, class R>
+__global__ __launch_bounds__(256) void rad_region_flux_kernel(RadStageArgs<S, R> a) {
+  const int N = a.nsub_ptr ? *a.nsub_ptr : a.nsub_val;
+  if (a.sub >= N) return;
+  const DevBox& b = a.b;
+  const RadParamsDev& p = a.p;
+  const int lo[3] = {a.rlo[0], a.rlo[1], a.rlo[2]}, hi[3] = {a.rhi[0], a.rhi[1], a.rhi[2]};
+  const int64_t total = region_face_count(lo, hi);
+  const double dt = (a.dt_ptr ? *a.dt_ptr : a.dt_val) / N;
+  const double w = 0.5 * dt * a.rw;
+  const R c = R(p.c), chat = R(p.chat), ratio = R(p.chat / p.c), cc = R(p.c * p.chat);
+  const bool tauc = p.tau_correction != 0;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+    const RegionFace rf = region_face(lo, hi, t);
+    const int d = rf.d;
+    // cell f along d (the face lies between cells f-1 and f); unit step e along d
+    const int ei = d == 0, ej = d == 1, ek = d == 2;
+    const int i = d == 0 ? (rf.side ? hi[0] : lo[0]) : lo[0] + rf.b;
+    const int j = d == 1 ? (rf.side ? hi[1] : lo[1]) : (d == 0 ? lo[1] + rf.b : lo[1] + rf.a);
+    const int k = d == 2 ? (rf.side ? hi[2] : lo[2]) : lo[2] + rf.a;
+    R Q[6][4];  // (E, f = F / (c E)) of cells f-3 .. f+2 along d
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      const int ii = i + ei * (s - 3), jj = j + ej * (s - 3), kk = k + ek * (s - 3);
+      const S* src = src_at(a.Uin, a.Ugh, b, ii, jj, kk);
+      const int64_t o = cell(b, ii, jj, kk);
+      const R Er = R(double(src[o]));
+      const R inv = R(1) / (c * Er);
+      Q[s][0] = Er;
+#pragma unroll
+      for (int v = 1; v < 4; ++v) Q[s][v] = R(double(src[o + v * b.vs])) * inv;
+    }
+    R sl[4], sr[4], tmp[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      recon5<R>(Q[0][v], Q[1][v], Q[2][v], Q[3][v], Q[4][v], p.recon, tmp[v], sl[v]);  // cell f-1, right
+      recon5<R>(Q[1][v], Q[2][v], Q[3][v], Q[4][v], Q[5][v], p.recon, sr[v], tmp[v]);  // cell f, left
+    }
+    R rl = R(0), rr = R(0);
+    if (tauc) {
+      rl = R(a.Ug[cell(b, i - ei, j - ej, k - ek)]);
+      rr = R(a.Ug[cell(b, i, j, k)]);
+    }
+    R F[4];
+    rad_face<R>(
+        sl, sr,
+        [&](R* cl, R* cr) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            cl[v] = Q[2][v];
+            cr[v] = Q[3][v];
+          }
+        },
+        rl, rr, R(d == 0 ? b.dx0 : (d == 1 ? b.dx1 : b.dx2)), d, p, c, chat, ratio, cc, F);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) a.reg[reg_slot(lo, hi, d, v, rf.side, rf.a, rf.b, 4)] += w * double(F[v]);
+  }
+}
 
 // Ghost fill guarded by the device substep count (skipped for unused substeps).
 template <class S>
