@@ -297,8 +297,9 @@ __device__ __forceinline__ void flatten_tile(const FlatArgs<S, R>& a, int tbx, i
   }
 }
 
-// Single-box flattening: 16 x 14 tiles on 256 threads (each phase one item
-// per thread, as in the stage).
+// Single-box flattening: 32 x 30 tiles on 1024 threads.  Each phase is one
+// item per thread (34 x 30 x-coefficients, 32 x 32 y-coefficients, a 372-cell
+// halo ring), and the halo ring per cell is half that of a 16 x 14 tile.
 constexpr int FTX = 32, FTY = 30, FNT = 1024;
 
 template <class S, class R>
