@@ -38,7 +38,7 @@ HYDRO_FLOPS_PER_CELL_STAGE = 45 * 15 + 106 * 3 + 13 + 57.5 + 11
 # FETCH_SIZE and WRITE_SIZE runs, scaled by the counts of a plain 2 GiB copy
 # (profiles/hydro_fp64_256_counters.md).  Valid only while the kernel sources
 # are the ones that were measured: reported as null once they change.
-STAGE_TRAFFIC = {"bytes_per_launch": 2.939e9, "sources_sha1": "db5c80a410a033b64d12446aa03042221189586d"}
+STAGE_TRAFFIC = {"bytes_per_launch": 2.937e9, "sources_sha1": "e41daf425547069ae2cb2c00e7b0a45e2c321b66"}
 KERNEL_SOURCES = ("paper_2110_01792_amd/csrc/hydro_kernels.hpp", "paper_2110_01792_amd/csrc/qk_device.hpp")
 
 
@@ -441,7 +441,7 @@ def main():
         "frac": round(h64["stage_achieved_TFLOPs"] / FP64_PEAK_TFLOPS, 4),
         "traffic": measured_traffic(),
         "traffic_unit": "HBM bytes per stage launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
-        "kernel": "stage_kernel<double,double,1|2,false> (fused hydro RK stage, 16x14 tiles)",
+        "kernel": "stage_kernel<double,double,1|2> (fused hydro RK stage, 16x14 tiles)",
         "flops_per_cell_launch": HYDRO_FLOPS_PER_CELL_STAGE,
         "bytes_per_cell_launch": HYDRO_BYTES_PER_CELL_STEP / 2,
         "hbm_achieved_GBs": round(h64["stage_achieved_GBs"], 1),
