@@ -20,9 +20,12 @@ def ctx():
     c.close()
 
 
-def test_mixed_hydro_shock_20_steps(ctx):
+@pytest.mark.parametrize("n", [64, 256], ids=["64", "256_full_size"])
+def test_mixed_hydro_shock_20_steps(ctx, n):
+    """The shock workload over 20 steps, at 64^3 and at the full 256^3."""
     torch = pytest.importorskip("torch")
-    b, U, p = inputs.hydro_shock(n=64)
+    oracle.set_threads(0)
+    b, U, p = inputs.hydro_shock(n=n)
     U = inputs.to_f32_and_back(U)
     o = U.copy()
     oracle.fill_ghosts(b, o)
@@ -45,9 +48,13 @@ def test_mixed_hydro_shock_20_steps(ctx):
     assert m_err <= 1e-5, (l1, li, m_err)
 
 
-def test_mixed_rhd_3_steps(ctx):
+@pytest.mark.parametrize("n", [32, 128], ids=["32", "128_config_size"])
+def test_mixed_rhd_3_steps(ctx, n):
+    """The log-normal RHD workload over 3 steps (30 radiation substeps), at
+    32^3 and at its 128^3 configuration size."""
     torch = pytest.importorskip("torch")
-    b, Ug, Ur, p = inputs.rhd_lognormal(n=32)
+    oracle.set_threads(0)
+    b, Ug, Ur, p = inputs.rhd_lognormal(n=n)
     Ug, Ur = inputs.to_f32_and_back(Ug), inputs.to_f32_and_back(Ur)
     og, orr = Ug.copy(), Ur.copy()
     for _ in range(3):
@@ -61,3 +68,7 @@ def test_mixed_rhd_3_steps(ctx):
     g, r = host(G), host(R)
     assert np.all(norm_l1(g, og, b)[[0, 4]] <= 1e-5), norm_l1(g, og, b)
     assert norm_l1(r, orr, b)[0] <= 1e-5, norm_l1(r, orr, b)
+    # F starts at zero and is bounded by c E_r: normalise by c sum(E_r)
+    I = b.interior()
+    ef = np.abs(r[I][1:] - orr[I][1:]).reshape(3, -1).sum(axis=1) / (p["c"] * np.abs(orr[I][0]).sum())
+    assert np.all(ef <= 1e-5), (norm_l1(r, orr, b), ef)
