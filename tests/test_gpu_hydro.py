@@ -194,6 +194,18 @@ def test_argument_errors(ctx):
                                           0.0, None, None))
 
 
+def test_nan_state_is_reported(ctx):
+    """A NaN in the state is caught by the same positivity tests (they are
+    written so that NaN fails them) and reported as QK_ENEGATIVE."""
+    b, U, p = inputs.hydro_smooth(n=16)
+    U[4, 5, 6, 7] = np.nan
+    Ud = dev(U)
+    ctx.fill_ghosts(b, Ud)
+    ctx.hydro_step(b, Ud, qb.hydro_params(p["gamma"], p["cfl"]), dt=1e-4)
+    assert ctx.sync_status() == qb.QK_ENEGATIVE
+    assert ctx.sync_status() == qb.QK_OK
+
+
 def test_negative_density_is_reported(ctx):
     b, U, p = inputs.hydro_smooth(n=16)
     U[0, 8, 8, 8] = -1.0
