@@ -162,8 +162,9 @@ qk_status quokka_batch_step(qk_ctx* ctx, const qk_box* boxes, int32_t nbox, void
                             void* const* U_rad, qk_precision prec, const qk_hydro_params* hp,
                             const qk_rad_params* rp, double* dt_host, void* stream);
 
-/* Tile edge (8 or 16 columns), z-chunk length and autotuning time (ms per
- * candidate stage) chosen for the last batch step.  The autotuner times the
+/* Tile family (8: 8 x 8 columns; 16: 16 x 16; 14: 16 x 14 with separate x
+ * and y sweep buffers), z-chunk length and autotuning time (ms per candidate
+ * stage) chosen for the last batch step.  The autotuner times the
  * side-effect-free first stages of each candidate on the caller's boxes the
  * first time a box-shape signature is seen; results persist in the JSON file
  * named by the environment variable QK_TUNE_CACHE, if set. */

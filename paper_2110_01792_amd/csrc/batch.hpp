@@ -6,7 +6,10 @@
 // (atomicAdd, one per item, every block exits once the counter passes the
 // list) and runs the same per-tile device function the single-box kernels
 // use, so a batched box and the same box run alone give identical bits.
-// Work lists are sorted largest tile first.  Ghost cells of a stage buffer are
+// Work lists are sorted largest tile first.  Tile families: 8 x 8 columns on
+// 64 threads and 16 x 16 on 256 (x and y sweeps share LDS buffers), and the
+// single-box shape 16 x 14 on 256 threads with separate x/y buffers (every
+// sweep phase one item per thread, three barriers per plane).  Ghost cells of a stage buffer are
 // read from the box's own fixed ghosts (ghost-source pointer), so no copies.
 #pragma once
 #include "rad_kernels.hpp"
@@ -43,8 +46,8 @@ __global__ void zero_counters_kernel(int* c, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0;
 }
 
-template <class S, class R, int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void batch_flatten_kernel(const BatchBox<S, R>* __restrict__ boxes,
+template <class S, class R, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void batch_flatten_kernel(const BatchBox<S, R>* __restrict__ boxes,
                                                                const WorkItem* __restrict__ items, int nitems,
                                                                int* counter, int stage) {
   __shared__ FlatSmem<R, TX, TY> sm;
@@ -61,15 +64,15 @@ __global__ __launch_bounds__(TX* TY) void batch_flatten_kernel(const BatchBox<S,
     a.b = bb.b;
     a.gm1 = bb.gamma - 1.0;
     a.zc = bb.zc_flat;
-    flatten_tile<S, R, TX, TY, TX * TY>(a, w.bx, w.by, w.bz, sm);
+    flatten_tile<S, R, TX, TY, NT>(a, w.bx, w.by, w.bz, sm);
   }
 }
 
-template <class S, class R, int TX, int TY, int STAGE>
-__global__ __launch_bounds__(TX* TY) void batch_stage_kernel(const BatchBox<S, R>* __restrict__ boxes,
+template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE>
+__global__ __launch_bounds__(NT) void batch_stage_kernel(const BatchBox<S, R>* __restrict__ boxes,
                                                              const WorkItem* __restrict__ items, int nitems,
                                                              int* counter, const double* dt_ptr, uint32_t* err) {
-  __shared__ HydroSmem<R, TX, TY, false> sm;
+  __shared__ HydroSmem<R, TX, TY, SPLIT> sm;
   __shared__ int slot;
   bool bad = false;
   for (;;) {
@@ -93,21 +96,21 @@ __global__ __launch_bounds__(TX* TY) void batch_stage_kernel(const BatchBox<S, R
     a.err = err;
     a.recon = bb.recon;
     a.reg = nullptr;
-    stage_tile<S, R, TX, TY, TX * TY, false, STAGE>(a, w.bx, w.by, w.bz, sm, bad);
+    stage_tile<S, R, TX, TY, NT, SPLIT, STAGE>(a, w.bx, w.by, w.bz, sm, bad);
     __syncthreads();
   }
   if (bad) atomicOr(err, ERR_NEG);
 }
 
-template <class S, class R, int TX, int TY, int STAGE>
-__global__ __launch_bounds__(TX* TY, 2) void batch_rad_kernel(const BatchBox<S, R>* __restrict__ boxes,
+template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE>
+__global__ __launch_bounds__(NT, 2) void batch_rad_kernel(const BatchBox<S, R>* __restrict__ boxes,
                                                               const WorkItem* __restrict__ items, int nitems,
                                                               int* counter, RadParamsDev p, const double* dt_ptr,
                                                               const int32_t* nsub_ptr, int sub, uint32_t* err,
                                                               uint32_t* iter_max) {
   const int N = *nsub_ptr;
   if (sub >= N) return;
-  __shared__ RadSmem<R, TX, TY, false> sm;
+  __shared__ RadSmem<R, TX, TY, SPLIT> sm;
   __shared__ int slot;
   bool bad = false, nfail = false;
   uint32_t itmax = 0;
@@ -134,12 +137,12 @@ __global__ __launch_bounds__(TX* TY, 2) void batch_rad_kernel(const BatchBox<S, 
     a.err = err;
     a.iter_max = iter_max;
     a.reg = nullptr;
-    itmax = max(itmax, rad_tile<S, R, TX, TY, TX * TY, false, STAGE>(a, w.bx, w.by, w.bz, N, sm, bad, nfail));
+    itmax = max(itmax, rad_tile<S, R, TX, TY, NT, SPLIT, STAGE>(a, w.bx, w.by, w.bz, N, sm, bad, nfail));
     __syncthreads();
   }
   if (bad) atomicOr(err, ERR_NEG);
   if (nfail) atomicOr(err, ERR_NEWTON);
-  if (STAGE == 2) block_umax_to<TX * TY>(itmax, iter_max);
+  if (STAGE == 2) block_umax_to<NT>(itmax, iter_max);
 }
 
 // Level CFL: max over every interior cell of every box of |v| + c_s (each box

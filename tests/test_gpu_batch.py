@@ -63,7 +63,7 @@ def test_batch_small_level_matches_oracle_over_graph_replays(ctx):
     for a, b in zip(dts, odts):
         assert abs(a - b) <= 1e-14 * b
     tile, zc, _ = ctx.batch_config()
-    assert tile in (8, 16) and zc >= 1
+    assert tile in (8, 14, 16) and zc >= 1
 
 
 def test_batch_hydro_only_equals_single_box_runs_bitwise(ctx):
