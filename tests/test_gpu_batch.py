@@ -167,6 +167,40 @@ def test_batch_autotune_cache_file(tmp_path):
         del os.environ["QK_TUNE_CACHE"]
 
 
+@pytest.mark.parametrize("tile", [8, 14, 16])
+def test_every_tile_family(tile, tmp_path):
+    """Each tile family (8 x 8, 16 x 14 with split buffers, 16 x 16), forced
+    through the autotuner's cache file: a level step of hydro and RHD boxes
+    matches the oracle's level step, and every hydro-only box equals the same
+    box advanced alone with the level dt, bit for bit."""
+    path = tmp_path / "tune.json"
+    os.environ["QK_TUNE_CACHE"] = str(path)
+    try:
+        boxes, Ugs, Urs, p, hp = inputs.batch_level(nbox=8, seed=36, edges=(8, 16, 24, 40))
+        c0 = qb.Context(0)
+        run_gpu(c0, boxes, Ugs, Urs, hp, p)  # tunes once and writes the signature's key
+        c0.close()
+        entry = json.loads(path.read_text())["quokka_batch_autotune"][0]
+        path.write_text(json.dumps({"quokka_batch_autotune": [dict(entry, tile=tile, zc=16)]}))
+        c = qb.Context(0)
+        gG, gR, dts = run_gpu(c, boxes, Ugs, Urs, hp, p)
+        assert c.batch_config()[:2] == (tile, 16)
+        oG = [u.copy() for u in Ugs]
+        oR = [None if u is None else u.copy() for u in Urs]
+        st = oracle.batch_step(boxes, oG, oR, hp["gamma"], hp["cfl"], p)
+        assert abs(dts[0] - st["dt"]) <= 1e-14 * st["dt"]
+        compare(boxes, gG, gR, oG, oR, what=f"tile {tile}")
+        hpp = qb.hydro_params(hp["gamma"], hp["cfl"])
+        for k, b in enumerate(boxes):
+            if Urs[k] is None:
+                U = dev(Ugs[k])
+                c.hydro_step(b, U, hpp, dt=dts[0])
+                assert np.array_equal(host(U), gG[k]), (tile, k, b.n)
+        c.close()
+    finally:
+        del os.environ["QK_TUNE_CACHE"]
+
+
 def test_batch_rejects_non_fixed_ghosts(ctx):
     torch = pytest.importorskip("torch")
     b = inputs.make_box(8)
