@@ -119,8 +119,9 @@ def load():
     return lib
 
 
-def make_box(b):
-    """QkBox from any object with n, ng, dx, bc (contiguous layout)."""
+def make_box(b, layout=(0, 0, 0)):
+    """QkBox from any object with n, ng, dx, bc; layout = (pitch_y, pitch_z,
+    var_stride) in elements, (0, 0, 0) for the contiguous layout."""
     q = QkBox()
     for d in range(3):
         q.n[d] = int(b.n[d])
@@ -128,7 +129,7 @@ def make_box(b):
         q.bc[d][0] = int(b.bc[d][0])
         q.bc[d][1] = int(b.bc[d][1])
     q.ng = int(b.ng)
-    q.pitch_y = q.pitch_z = q.var_stride = 0
+    q.pitch_y, q.pitch_z, q.var_stride = (int(x) for x in layout)
     return q
 
 
@@ -174,11 +175,28 @@ def _prec_of(t):
 
 
 def _check_state(t, b, nvar):
+    """Check a device state tensor of shape (nvar, NZ, NY, NX) and return its
+    layout (pitch_y, pitch_z, var_stride): (0, 0, 0) when contiguous, else
+    the strides of a padded view (x contiguous, each outer stride at least the
+    extent it spans), which the library addresses through the box pitches."""
     shape = (nvar, b.n[2] + 2 * b.ng, b.n[1] + 2 * b.ng, b.n[0] + 2 * b.ng)
     if tuple(t.shape) != shape:
         raise ValueError(f"state shape {tuple(t.shape)} != {shape}")
-    if not t.is_contiguous() or t.device.type != "cuda":
-        raise ValueError("state must be a contiguous device tensor")
+    if t.device.type != "cuda":
+        raise ValueError("state must be a device tensor")
+    if t.is_contiguous():
+        return (0, 0, 0)
+    sv, sz, sy, sx = t.stride()
+    if sx != 1 or sy < shape[3] or sz < sy * shape[2] or sv < sz * shape[1]:
+        raise ValueError(f"state strides {t.stride()} are not a padded x-contiguous layout")
+    return (sy, sz, sv)
+
+
+def _same_layout(*layouts):
+    """Gas and radiation states of one call share the box's pitches."""
+    if any(l != layouts[0] for l in layouts[1:]):
+        raise ValueError(f"states of one box must share one layout, got {layouts}")
+    return layouts[0]
 
 
 class Context:
@@ -208,22 +226,22 @@ class Context:
             raise QuokkaError(st, self.lib.quokka_last_error(self.h).decode())
 
     def fill_ghosts(self, b, U, stream=None):
-        _check_state(U, b, U.shape[0])
-        self._ok(self.lib.quokka_fill_ghosts(self.h, ctypes.byref(make_box(b)), _ptr(U), int(U.shape[0]),
+        lay = _check_state(U, b, U.shape[0])
+        self._ok(self.lib.quokka_fill_ghosts(self.h, ctypes.byref(make_box(b, lay)), _ptr(U), int(U.shape[0]),
                                              _prec_of(U), _stream(stream)))
 
     def compute_dt(self, b, Ug, hp=None, rp=None, dt_dev=None, nsub_dev=None, host=True, stream=None):
-        _check_state(Ug, b, 5)
+        lay = _check_state(Ug, b, 5)
         out = ctypes.c_double(0.0)
-        self._ok(self.lib.quokka_compute_dt(self.h, ctypes.byref(make_box(b)), _ptr(Ug), _prec_of(Ug),
+        self._ok(self.lib.quokka_compute_dt(self.h, ctypes.byref(make_box(b, lay)), _ptr(Ug), _prec_of(Ug),
                                             ctypes.byref(hp) if hp is not None else None,
                                             ctypes.byref(rp) if rp is not None else None, _ptr(dt_dev),
                                             _ptr(nsub_dev), ctypes.byref(out) if host else None, _stream(stream)))
         return out.value if host else None
 
     def hydro_step(self, b, Ug, hp, dt_dev=None, dt=0.0, dt_next_dev=None, stream=None):
-        _check_state(Ug, b, 5)
-        self._ok(self.lib.quokka_hydro_step(self.h, ctypes.byref(make_box(b)), _ptr(Ug), _prec_of(Ug),
+        lay = _check_state(Ug, b, 5)
+        self._ok(self.lib.quokka_hydro_step(self.h, ctypes.byref(make_box(b, lay)), _ptr(Ug), _prec_of(Ug),
                                             ctypes.byref(hp), _ptr(dt_dev), float(dt), _ptr(dt_next_dev),
                                             _stream(stream)))
 
@@ -232,10 +250,10 @@ class Context:
         """Hydro step adding weight * dt/2 * F of both stages at the faces
         bounding region [lo, hi) to the FP64 device register `reg`."""
         import torch
-        _check_state(Ug, b, 5)
+        lay = _check_state(Ug, b, 5)
         if reg.dtype != torch.float64 or reg.numel() != region_size(lo, hi) or not reg.is_cuda:
             raise ValueError("register must be a float64 device tensor of region_size(lo, hi) elements")
-        self._ok(self.lib.quokka_hydro_step_reg(self.h, ctypes.byref(make_box(b)), _ptr(Ug), _prec_of(Ug),
+        self._ok(self.lib.quokka_hydro_step_reg(self.h, ctypes.byref(make_box(b, lay)), _ptr(Ug), _prec_of(Ug),
                                                 ctypes.byref(hp), _ptr(dt_dev), float(dt),
                                                 ctypes.byref(make_region(lo, hi)), _ptr(reg), float(weight),
                                                 _stream(stream)))
@@ -245,56 +263,55 @@ class Context:
         weight * dt_sub/2 * F of every stage at the faces bounding [lo, hi)
         to the FP64 device register `reg` (4 variables)."""
         import torch
-        _check_state(Ug, b, 5)
-        _check_state(Ur, b, 4)
+        lay = _same_layout(_check_state(Ug, b, 5), _check_state(Ur, b, 4))
         if reg.dtype != torch.float64 or reg.numel() != region_size(lo, hi, 4) or not reg.is_cuda:
             raise ValueError("register must be a float64 device tensor of region_size(lo, hi, 4) elements")
-        self._ok(self.lib.quokka_rad_step_reg(self.h, ctypes.byref(make_box(b)), _ptr(Ug), _ptr(Ur), _prec_of(Ug),
+        self._ok(self.lib.quokka_rad_step_reg(self.h, ctypes.byref(make_box(b, lay)), _ptr(Ug), _ptr(Ur), _prec_of(Ug),
                                               ctypes.byref(rp), None, None, float(dt),
                                               ctypes.byref(make_region(lo, hi)), _ptr(reg), float(weight),
                                               _stream(stream)))
 
     def average_down(self, fb, Uf, cb, Uc, off, nvar=5, stream=None):
-        _check_state(Uf, fb, nvar)
-        _check_state(Uc, cb, nvar)
+        lf = _check_state(Uf, fb, nvar)
+        lc = _check_state(Uc, cb, nvar)
         o = (ctypes.c_int32 * 3)(*[int(x) for x in off])
-        self._ok(self.lib.quokka_average_down(self.h, ctypes.byref(make_box(fb)), _ptr(Uf),
-                                              ctypes.byref(make_box(cb)), _ptr(Uc), o, int(nvar), _prec_of(Uf),
+        self._ok(self.lib.quokka_average_down(self.h, ctypes.byref(make_box(fb, lf)), _ptr(Uf),
+                                              ctypes.byref(make_box(cb, lc)), _ptr(Uc), o, int(nvar), _prec_of(Uf),
                                               _stream(stream)))
 
     def prolong(self, cb, Uc0, Uc1, alpha, fb, Uf, off, nvar=5, interior=False, stream=None):
-        for t, b in ((Uc0, cb), (Uc1, cb), (Uf, fb)):
-            _check_state(t, b, nvar)
+        lc = _same_layout(_check_state(Uc0, cb, nvar), _check_state(Uc1, cb, nvar))
+        lf = _check_state(Uf, fb, nvar)
         o = (ctypes.c_int32 * 3)(*[int(x) for x in off])
-        self._ok(self.lib.quokka_prolong(self.h, ctypes.byref(make_box(cb)), _ptr(Uc0), _ptr(Uc1), float(alpha),
-                                         ctypes.byref(make_box(fb)), _ptr(Uf), o, int(nvar), int(bool(interior)),
+        self._ok(self.lib.quokka_prolong(self.h, ctypes.byref(make_box(cb, lc)), _ptr(Uc0), _ptr(Uc1), float(alpha),
+                                         ctypes.byref(make_box(fb, lf)), _ptr(Uf), o, int(nvar), int(bool(interior)),
                                          _prec_of(Uf), _stream(stream)))
 
     def reflux(self, cb, Uc, lo, hi, reg_c, fb, reg_f, nvar=5, stream=None):
-        _check_state(Uc, cb, nvar)
-        self._ok(self.lib.quokka_reflux(self.h, ctypes.byref(make_box(cb)), _ptr(Uc),
+        lc = _check_state(Uc, cb, nvar)
+        self._ok(self.lib.quokka_reflux(self.h, ctypes.byref(make_box(cb, lc)), _ptr(Uc),
                                         ctypes.byref(make_region(lo, hi)), _ptr(reg_c), ctypes.byref(make_box(fb)),
                                         _ptr(reg_f), int(nvar), _prec_of(Uc), _stream(stream)))
 
     def rad_step(self, b, Ug, Ur, rp, dt_dev=None, nsub_dev=None, dt=0.0, stream=None):
-        _check_state(Ug, b, 5)
-        _check_state(Ur, b, 4)
-        self._ok(self.lib.quokka_rad_step(self.h, ctypes.byref(make_box(b)), _ptr(Ug), _ptr(Ur), _prec_of(Ug),
+        lay = _same_layout(_check_state(Ug, b, 5), _check_state(Ur, b, 4))
+        self._ok(self.lib.quokka_rad_step(self.h, ctypes.byref(make_box(b, lay)), _ptr(Ug), _ptr(Ur), _prec_of(Ug),
                                           ctypes.byref(rp), _ptr(dt_dev), _ptr(nsub_dev), float(dt),
                                           _stream(stream)))
 
     def rhd_step(self, b, Ug, Ur, rp, host_dt=False, stream=None):
-        _check_state(Ug, b, 5)
-        _check_state(Ur, b, 4)
+        lay = _same_layout(_check_state(Ug, b, 5), _check_state(Ur, b, 4))
         out = ctypes.c_double(0.0)
-        self._ok(self.lib.quokka_rhd_step(self.h, ctypes.byref(make_box(b)), _ptr(Ug), _ptr(Ur), _prec_of(Ug),
+        self._ok(self.lib.quokka_rhd_step(self.h, ctypes.byref(make_box(b, lay)), _ptr(Ug), _ptr(Ur), _prec_of(Ug),
                                           ctypes.byref(rp), ctypes.byref(out) if host_dt else None,
                                           _stream(stream)))
         return out.value if host_dt else None
 
     def batch_step(self, boxes, Ugs, Urs, hp, rp, host_dt=True, stream=None):
         n = len(boxes)
-        arr = (QkBox * n)(*[make_box(b) for b in boxes])
+        lays = [_check_state(g, b, 5) if r is None else _same_layout(_check_state(g, b, 5), _check_state(r, b, 4))
+                for b, g, r in zip(boxes, Ugs, Urs)]
+        arr = (QkBox * n)(*[make_box(b, l) for b, l in zip(boxes, lays)])
         gp = (ctypes.c_void_p * n)(*[u.data_ptr() for u in Ugs])
         rpp = (ctypes.c_void_p * n)(*[(u.data_ptr() if u is not None else None) for u in Urs])
         out = ctypes.c_double(0.0)

@@ -41,3 +41,15 @@ def worst_cell(g, o, b):
     d = np.abs(g[I] - o[I])
     idx = np.unravel_index(np.argmax(d), d.shape)
     return idx, g[I][idx], o[I][idx]
+
+
+def padded_view(U, pad=(3, 1, 2)):
+    """A copy of the device array U inside a larger NaN-filled array (pad =
+    extra x elements per row, rows per plane, planes per variable): returns
+    (storage, strided view of U's shape)."""
+    import torch
+    nv, NZ, NY, NX = U.shape
+    big = torch.full((nv, NZ + pad[2], NY + pad[1], NX + pad[0]), float("nan"), dtype=U.dtype, device=U.device)
+    view = big[:, :NZ, :NY, :NX]
+    view.copy_(U)
+    return big, view

@@ -7,7 +7,7 @@ import pytest
 import oracle
 from paper_2110_01792_amd import binding as qb
 from paper_2110_01792_amd import inputs
-from tests.gpu_util import dev, host, rel_linf, worst_cell
+from tests.gpu_util import dev, host, padded_view, rel_linf, worst_cell
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-10
@@ -254,3 +254,23 @@ def test_rhd_other_closures(ctx, closure):
     assert st == qb.QK_OK
     og, orr, _ = oracle_rhd(b, Ug, Ur, p)
     check_pair((g, r), (og, orr), b, f"closure {closure}")
+
+
+def test_rhd_padded_layout_equals_contiguous_bitwise(ctx):
+    """Gas and radiation states in one padded layout (shared pitches) give the
+    bits of the contiguous layout over an RHD step; states of one box in
+    different layouts are refused on the host."""
+    b, Ug, Ur, p = inputs.rhd_lognormal(n=20, seed=43)
+    rp = qb.rad_params(p)
+    G, R = dev(Ug), dev(Ur)
+    bg, PG = padded_view(dev(Ug))
+    br, PR = padded_view(dev(Ur))
+    for g, r in ((G, R), (PG, PR)):
+        ctx.fill_ghosts(b, g)
+        ctx.fill_ghosts(b, r)
+        ctx.rhd_step(b, g, r, rp)
+    assert ctx.sync_status() == qb.QK_OK
+    assert np.array_equal(host(G), host(PG.contiguous()))
+    assert np.array_equal(host(R), host(PR.contiguous()))
+    with pytest.raises(ValueError):
+        ctx.rhd_step(b, G, PR, rp)
