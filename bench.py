@@ -370,6 +370,8 @@ def run_only(args, torch, qb, inputs):
                "source": bench_rhd(ctx, qb, inputs, torch, args.steps, args.warmup, f64, source=True)}
     elif args.only == "amr":
         out = bench_amr(ctx, qb, inputs, torch, args.steps, args.warmup)
+    elif args.only == "batch32":
+        out = bench_batch(ctx, qb, inputs, torch, args.steps, f32)
     else:
         out = bench_batch(ctx, qb, inputs, torch, args.steps, f64)
     ctx.close()
@@ -382,7 +384,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--only", default="all", choices=["all", "hydro", "rhd", "hydro32", "rhd32", "sedov", "rhdplm", "rhdvar", "amr", "batch", "copy"],
+    ap.add_argument("--only", default="all", choices=["all", "hydro", "rhd", "hydro32", "rhd32", "sedov", "rhdplm", "rhdvar", "amr", "batch", "batch32", "copy"],
                     help="run one section only (for profiler runs); 'copy' runs a plain 2 GiB device copy used "
                          "to calibrate the HBM byte counters")
     args = ap.parse_args()
