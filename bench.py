@@ -28,11 +28,12 @@ METRIC = "cell updates/s (hydro, RHD) 256^3 on 1 MI355X; % of HBM roofline; FP32
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64 (FMA counted as two)
 HYDRO_BYTES_PER_CELL_STEP = 200.0  # stage 1: read 40 + write 40; stage 2: read 80 + write 40 (FP64)
-# FP64 operations (add, sub, mul, div, sqrt each one) of one cell in one fused
-# RK stage, each interface and cell counted once: PPM + flattening blend
-# 45 x 15 (5 variables, 3 axes), HLLC 106 x 3 faces, conserved -> primitive
-# 13, flux differences and RK update 57.5 (mean of the stages), CFL signal of
-# stage 2 11 (mean).
+# FP64 operations (add, sub, mul, min, max, div, sqrt each one) of one cell in
+# one fused RK stage, as the method states them, each interface and cell
+# counted once: PPM 45 x 15 (5 variables, 3 axes; the flattening blend, an
+# identity where chi = 1, is not counted), HLLC 106 x 3 faces, conserved ->
+# primitive 13, flux differences and RK update 57.5 (mean of the stages), CFL
+# signal of stage 2 11 (mean).
 HYDRO_FLOPS_PER_CELL_STAGE = 45 * 15 + 106 * 3 + 13 + 57.5 + 11
 # HBM bytes per stage launch (mean of stages 1 and 2) from rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE runs, scaled by the counts of a plain 2 GiB copy
