@@ -201,13 +201,13 @@ qk_status quokka_rad_step_reg(qk_ctx* ctx, const qk_box* box, void* U_gas, void*
                               const qk_region* region, double* reg, double weight, void* stream);
 
 /* Coarse cells off + (I, J, K), 0 <= I < n_fine/2 (per axis), get the mean of
- * their 8 fine children (nvar variables; same precision on both levels).
+ * their 8 fine children (nvar variables, 1..16; same precision on both levels).
  * Fine extents must be even and the footprint inside the coarse interior. */
 qk_status quokka_average_down(qk_ctx* ctx, const qk_box* fine, const void* U_fine, const qk_box* coarse,
                               void* U_coarse, const int32_t off[3], int32_t nvar, qk_precision prec, void* stream);
 
 /* Fine cells from the coarse level at time (1 - alpha) t0 + alpha t1 (states
- * U_c0 and U_c1, alpha in [0, 1]): the parent's value plus a quarter of the
+ * U_c0 and U_c1 of nvar variables, 1..16; alpha in [0, 1]): the parent's value plus a quarter of the
  * MC-limited slope per axis toward the child's side, which keeps every
  * parent's mean.  Fine cell 0 lies in coarse cell off.  interior == 0 fills the
  * fine ghost layers only (fill-patch of a fine box with FIXED ghosts); != 0
