@@ -2,7 +2,8 @@
 
 Argument marshalling only: every step of the update runs in the HIP library.
 State arguments are torch tensors on a ROCm device (float64 for F64, float32
-for MIXED), shape (nvar, nz+2ng, ny+2ng, nx+2ng), contiguous; PyTorch supplies
+for MIXED), shape (nvar, nz+2ng, ny+2ng, nx+2ng), contiguous or a padded view
+with x contiguous (its strides become the box pitches); PyTorch supplies
 device memory and streams, nothing else.  If the library is missing this
 module raises; there is no fallback.
 """
