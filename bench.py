@@ -39,17 +39,25 @@ HYDRO_FLOPS_PER_CELL_STAGE = 45 * 15 + 106 * 3 + 13 + 57.5 + 11
 # FETCH_SIZE and WRITE_SIZE runs, scaled by the counts of a plain 2 GiB copy
 # (profiles/hydro_fp64_256_counters.md).  Valid only while the kernel sources
 # are the ones that were measured: reported as null once they change.
+# The same runs give the stage's VALU issue rate (SQ_INSTS_VALU against 1024
+# SIMDs x 2.4 GHz / 4 cycles per wave64 instruction, mean of the two stages).
+STAGE_VALU_ISSUE_FRAC = 0.584
 STAGE_TRAFFIC = {"bytes_per_launch": 2.937e9, "sources_sha1": "e41daf425547069ae2cb2c00e7b0a45e2c321b66"}
 KERNEL_SOURCES = ("paper_2110_01792_amd/csrc/hydro_kernels.hpp", "paper_2110_01792_amd/csrc/qk_device.hpp")
 
 
-def measured_traffic():
+def counters_valid():
+    """True while the kernel sources are the ones the counters were taken on."""
     import hashlib
     h = hashlib.sha1()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return STAGE_TRAFFIC["bytes_per_launch"] if h.hexdigest() == STAGE_TRAFFIC["sources_sha1"] else None
+    return h.hexdigest() == STAGE_TRAFFIC["sources_sha1"]
+
+
+def measured_traffic():
+    return STAGE_TRAFFIC["bytes_per_launch"] if counters_valid() else None
 
 
 def log(*a):
@@ -449,6 +457,9 @@ def main():
         "bytes_per_cell_launch": HYDRO_BYTES_PER_CELL_STEP / 2,
         "hbm_achieved_GBs": round(h64["stage_achieved_GBs"], 1),
         "hbm_frac": round(h64["stage_achieved_GBs"] / HBM_PEAK_GBS, 4),
+        "valu_issue_frac": STAGE_VALU_ISSUE_FRAC if counters_valid() else None,
+        "valu_issue_note": "rocprofv3 SQ_INSTS_VALU of the same kernel (profiles/hydro_fp64_256_counters.md): "
+                           "share of the chip's wave64 VALU issue slots the stage uses; no FMA contraction",
     }
     line = {
         "metric": METRIC,
