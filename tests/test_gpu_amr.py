@@ -101,12 +101,14 @@ def test_prolong_and_average_down_match_oracle(ctx):
     assert np.array_equal(host(cd), co)
 
 
-def test_two_level_step_matches_oracle_and_conserves(ctx):
+@pytest.mark.parametrize("n,m,off", [(16, 16, (4, 4, 4)), (64, 72, (10, 14, 20))], ids=["16", "64_multi_tile"])
+def test_two_level_step_matches_oracle_and_conserves(ctx, n, m, off):
     """Two coarse steps of the two-level scheme (coarse step, two fine steps
     with ghosts from the coarse level in space and time, average-down,
     reflux) on the GPU against the oracle, and the composite totals kept to
-    round-off."""
-    cb, Uc, fb, Uf, off, p = inputs.two_level()
+    round-off.  The larger case spans several stage tiles and z-chunks on
+    both levels, with a footprint that cuts through tiles."""
+    cb, Uc, fb, Uf, off, p = inputs.two_level(n=n, m=m, off=off)
     oracle.average_down(fb, Uf, cb, Uc, off)
     t0 = composite_totals(cb, Uc, fb, Uf, off)
     Cd, Fd = dev(Uc), dev(Uf)
@@ -122,12 +124,12 @@ def test_two_level_step_matches_oracle_and_conserves(ctx):
     assert np.all(np.abs(t1 - t0) / np.abs(t0).max() < 1e-14)
 
 
-def test_radiation_two_level_step_matches_oracle_and_conserves(ctx):
-    """Radiation on two levels (transport only, kappa = 0): registers recorded
-    by the radiation stage kernel over every substep, prolongation and
-    average-down of 4 variables, reflux; GPU against the oracle and the
-    totals of E_r and F kept to round-off."""
-    cb, Gc, Rc, fb, Gf, Rf, off, hp, p = inputs.two_level(rad=True)
+@pytest.mark.parametrize("n,m,off", [(16, 16, (4, 4, 4)), (48, 40, (6, 10, 14))], ids=["16", "48_multi_tile"])
+def test_radiation_two_level_step_matches_oracle_and_conserves(ctx, n, m, off):
+    """Radiation on two levels (transport only, kappa = 0): registers of every
+    substep's stages, prolongation and average-down of 4 variables, reflux;
+    GPU against the oracle and the totals of E_r and F kept to round-off."""
+    cb, Gc, Rc, fb, Gf, Rf, off, hp, p = inputs.two_level(n=n, m=m, off=off, rad=True)
     oracle.average_down(fb, Rf, cb, Rc, off, nvar=4)
     oracle.average_down(fb, Gf, cb, Gc, off, nvar=5)
     t0 = composite_totals_n(cb, Rc, fb, Rf, off)
