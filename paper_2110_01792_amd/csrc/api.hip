@@ -253,6 +253,8 @@ struct Launch {
   int gx, gy, gz, zc;
 };
 
+constexpr int kStageChunkPlanes = 16;  // z-chunk length the stage kernels aim at (see plan)
+
 // Blocks of `kernel` resident on the whole device at once (occupancy x CUs).
 template <class K>
 int resident_grid(K kernel, int threads) {
@@ -267,16 +269,21 @@ int resident_grid(K kernel, int threads) {
 // "generations" of `resident` at a time; the chunk count c minimises
 // generations x (planes per chunk + the chunk's z prologue, ~2.5 planes),
 // with at least 8 planes per chunk, so that the last generation is not a
-// nearly empty one.
-Launch plan(int n0, int n1, int n2, int tx, int ty, int resident) {
+// nearly empty one.  zc_target > 0 asks for chunks of at most about that many
+// planes: the stage kernels run best with ~16 (measured at 256^3: hydro stage
+// 1.44 -> 1.37 ms, radiation stages 1.29/1.69 -> 1.25/1.63 ms against the
+// model's 52-plane chunks, whose long blocks finish unevenly at the end of a
+// launch); the flattening pass is best with the model's choice.
+Launch plan(int n0, int n1, int n2, int tx, int ty, int resident, int zc_target = 0) {
   Launch L;
   L.gx = (n0 + tx - 1) / tx;
   L.gy = (n1 + ty - 1) / ty;
   const int64_t nxy = (int64_t)L.gx * L.gy;
-  const int cmax = std::max(1, n2 / 8);
+  const int cmin = zc_target > 0 ? std::max(1, (n2 + zc_target / 2) / zc_target) : 1;
+  const int cmax = std::max(cmin, n2 / 8);
   double best = 1e300;
-  int bc = 1;
-  for (int c = 1; c <= cmax; ++c) {
+  int bc = cmin;
+  for (int c = cmin; c <= cmax; ++c) {
     const int zc = (n2 + c - 1) / c, gz = (n2 + zc - 1) / zc;
     const int64_t gens = (nxy * gz + resident - 1) / std::max(1, resident);
     const double cost = (double)gens * (zc + 2.5);
@@ -311,7 +318,7 @@ void launch_stage(const HostBox& hb, const S* Uin, const S* Un, S* Uout, const R
                   hipStream_t s, const RegRec* rec = nullptr) {
   const DevBox& d = hb.d;
   static const int res = resident_grid(stage_kernel<S, R, STAGE>, SNT);
-  Launch L = plan(d.n0, d.n1, d.n2, STX, STY, res);
+  Launch L = plan(d.n0, d.n1, d.n2, STX, STY, res, kStageChunkPlanes);
   StageArgs<S, R> a;
   a.Uin = Uin;
   a.Ugh = nullptr;
