@@ -38,12 +38,14 @@ HYDRO_FLOPS_PER_CELL_STAGE = 45 * 15 + 106 * 3 + 13 + 57.5 + 11
 # HBM bytes per stage launch (mean of stages 1 and 2) from rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE runs, scaled by the counts of a plain 2 GiB copy
 # (profiles/hydro_fp64_256_counters.md).  Valid only while the kernel sources
-# are the ones that were measured: reported as null once they change.
+# and launch plan are the ones that were measured: reported as null once they change.
 # The same runs give the stage's VALU issue rate (SQ_INSTS_VALU against 1024
 # SIMDs x 2.4 GHz / 4 cycles per wave64 instruction, mean of the two stages).
-STAGE_VALU_ISSUE_FRAC = 0.584
-STAGE_TRAFFIC = {"bytes_per_launch": 2.937e9, "sources_sha1": "e41daf425547069ae2cb2c00e7b0a45e2c321b66"}
-KERNEL_SOURCES = ("paper_2110_01792_amd/csrc/hydro_kernels.hpp", "paper_2110_01792_amd/csrc/qk_device.hpp")
+STAGE_VALU_ISSUE_FRAC = 0.641
+STAGE_TRAFFIC = {"bytes_per_launch": 2.923e9, "sources_sha1": "25609dea3e5541bcec44998fa8767bf1f264f0b2"}
+# The stage kernel's sources and its launch plan (the z-chunk length changes the traffic).
+KERNEL_SOURCES = ("paper_2110_01792_amd/csrc/hydro_kernels.hpp", "paper_2110_01792_amd/csrc/qk_device.hpp",
+                  "paper_2110_01792_amd/csrc/api.hip")
 
 
 def counters_valid():
