@@ -1,0 +1,34 @@
+"""Host-side checks of the benchmark script (no GPU): the committed counter
+figures belong to the committed kernel sources, and a multi-GPU request is
+refused before anything touches a device."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_counter_figures_belong_to_the_committed_kernels():
+    """The traffic and issue figures the roofline reports were measured on these
+    kernel sources and launch plan (profiles/hydro_fp64_256_counters.md)."""
+    for f in bench.KERNEL_SOURCES:
+        assert os.path.exists(os.path.join(ROOT, f)), f
+    assert bench.counters_valid()
+    assert bench.measured_traffic() == bench.STAGE_TRAFFIC["bytes_per_launch"]
+    assert 0.0 < bench.STAGE_VALU_ISSUE_FRAC < 1.0
+
+
+def test_flop_and_byte_counts_per_cell():
+    assert bench.HYDRO_FLOPS_PER_CELL_STAGE == 45 * 15 + 106 * 3 + 13 + 57.5 + 11
+    assert bench.HYDRO_BYTES_PER_CELL_STEP == 200.0
+    assert bench.RHD_BYTES_PER_CELL_STEP == 200.0 + 10 * (72.0 + 168.0)
+
+
+def test_more_than_one_gpu_is_refused_without_a_device():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
