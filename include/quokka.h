@@ -61,6 +61,10 @@ typedef struct {
   int64_t pitch_y;     /* element stride between rows;   0 = n[0] + 2 ng          */
   int64_t pitch_z;     /* element stride between planes; 0 = pitch_y (n[1]+2ng) */
   int64_t var_stride;  /* element stride between variables; 0 = pitch_z (n[2]+2ng) */
+  /* Size limits (QK_EINVAL beyond them): 5 * var_stride <= 2^40 elements, and
+     the one-tile-per-block stage grid, (n[0]/16)(n[1]/14)(n[2]/8) blocks of 256
+     work-items rounded up, within 2^32 - 1 work-items (the flattening grid,
+     32 x 30 tiles of 1024, likewise); 4096^3 is beyond it, 2048^3 within.   */
   double dx[3];        /* cell widths                                           */
   int32_t bc[3][2];    /* qk_bc per axis, lo then hi                            */
 } qk_box;

@@ -161,6 +161,18 @@ qk_status check_box(qk_ctx* ctx, const qk_box* b, HostBox& hb) {
   const int64_t vs = b->var_stride ? b->var_stride : pz * NZ;
   if (py < NX || pz < py * NY || vs < pz * NZ) return fail(ctx, QK_EINVAL, "pitches too small for the extents");
   if (vs * 5 > ((int64_t)1 << 40)) return fail(ctx, QK_EINVAL, "box too large");
+  // A dispatch covers at most 2^32 - 1 work-items.  The stage and flattening
+  // launches give each block one tile and one z-chunk, and the launch plan
+  // never cuts chunks shorter than 8 planes, so this bounds both grids.
+  {
+    auto blocks = [](int64_t m0, int64_t m1, int64_t m2, int tx, int ty) {
+      return ((m0 + tx - 1) / tx) * ((m1 + ty - 1) / ty) * std::max<int64_t>(1, (m2 + 7) / 8);
+    };
+    const int64_t lim = 0xffffffffLL;
+    if (blocks(b->n[0], b->n[1], b->n[2], STX, STY) * SNT > lim ||
+        blocks(b->n[0] + 2, b->n[1] + 2, b->n[2] + 2, FTX, FTY) * FNT > lim)
+      return fail(ctx, QK_EINVAL, "box too large for one launch grid");
+  }
   DevBox& d = hb.d;
   d.n0 = b->n[0];
   d.n1 = b->n[1];

@@ -221,7 +221,8 @@ def test_box_limits_are_rejected_before_any_launch(ctx):
     host.  The state pointers are NULL, so a missing check could not reach a
     kernel either: each call must fail with the box's own message."""
     hp = qb.hydro_params(1.4, 0.3)
-    cases = [((0, 8, 8), 4, "extent"), ((8, 8, 8), 3, "ng"), ((16384, 16384, 16384), 4, "too large")]
+    cases = [((0, 8, 8), 4, "extent"), ((8, 8, 8), 3, "ng"), ((16384, 16384, 16384), 4, "too large"),
+             ((4096, 4096, 4096), 4, "launch grid"), ((8192, 8192, 512), 4, "launch grid")]
     for n, ng, what in cases:
         b = inputs.Box(n, ng, (1.0, 1.0, 1.0), ((0, 0), (0, 0), (0, 0)))
         st = ctx.lib.quokka_hydro_step(ctx.h, qb.make_box(b), None, 0, hp, None, 1e-3, None, None)
