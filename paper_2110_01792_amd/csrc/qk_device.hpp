@@ -4,6 +4,7 @@
 // R is the reconstruction/flux arithmetic type (double on the FP64 path,
 // float on the mixed path); anything marked "double" stays FP64 on both.
 #pragma once
+#include <limits>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -200,37 +201,52 @@ __device__ __forceinline__ float chi_tilde<float>(float pm2, float pm1, float pp
 // Radiation: M1 closure and HLL flux (Section 2.2.2, eq. M1_closure).
 // A face state is (E, f) with f = F/(c E); F = c E f.
 // ---------------------------------------------------------------------------
-// Eddington factor chi(f), f = min(|f|, 1) (Section 2.2.2): 0 Levermore
-// (3 + 4 f^2) / (5 + 2 sqrt(4 - 3 f^2)); 1 Eddington, 1/3; 2 Minerbo in the
-// polynomial form 1/3 + (2/15)(3 f^2 - f^3 + 3 f^4) (Cernohorsky & Bludman
-// 1994).  The closure enters the flux only through this function.
+// Eddington tensor P/E = a I + b n n, a = (1 - chi)/2, b = (3 chi - 1)/2
+// (Section 2.2.2), chi the Eddington factor of f = min(|f|, 1).  b vanishes
+// like f^2; the kernels form k = b / f^2 from f2 = f^2:
+//   0 Levermore, chi = (3 + 4 f^2) / (5 + 2 s) with s = sqrt(4 - 3 f^2):
+//     b = (4 + 12 f^2 - 2 s) / (2 (5 + 2 s)), and 4 - 2 s = 12 f^2 / (4 + 2 s)
+//     turns this into b = 3 f^2 / (2 + s), so k = 3 / (2 + s);
+//   1 Eddington, chi = 1/3: k = 0;
+//   2 Minerbo in the polynomial form chi = 1/3 + (2/15)(3 f^2 - f^3 + 3 f^4)
+//     (Cernohorsky & Bludman 1994): k = (3 - f + 3 f^2) / 5.
+// Then b = f2 k and a = (1 - b) / 3.  Levermore takes one quotient here,
+// where chi and b / |f|^2 took two, and b has no cancellation near f = 0.
+// The closure enters the flux only through this function.
 template <class R>
-__device__ __forceinline__ R closure_chi(R f, int closure) {
-  const R f2 = f * f;
-  if (closure == 1) return R(1.0 / 3.0);
-  if (closure == 2) return R(1.0 / 3.0) + R(2.0 / 15.0) * ((R(3) * f2 - f2 * f) + R(3) * f2 * f2);
-  return (R(3) + R(4) * f2) / (R(5) + R(2) * sqrt(R(4) - R(3) * f2));
+__device__ __forceinline__ R closure_k(R f2, int closure) {
+  if (closure == 1) return R(0);
+  if (closure == 2) return ((R(3) - sqrt(f2)) + R(3) * f2) * R(0.2);
+  return R(3) / (R(2) + sqrt(R(4) - R(3) * f2));
+}
+
+// |f| > 1 decided on ff = f.f: sqrt is monotone and correctly rounded, and
+// sqrt(ff) rounds to a value above 1 exactly when ff exceeds the next number
+// above 1, so this is the same test without the square root.
+template <class R>
+__device__ __forceinline__ bool f_above_one(R ff) {
+  return ff > R(1) + std::numeric_limits<R>::epsilon();
 }
 
 // Row `d` of the Eddington tensor P/E; Tdd = P_dd/E (the HLL speed is
-// chat sqrt(Tdd)).  Cartesian components of f are fx, fy, fz and fn = |f|;
-// f may exceed 1 only in fallback states, where the closure uses
-// min(|f|, 1) (Section 2.2.2).
+// chat sqrt(Tdd)).  Cartesian components of f are fx, fy, fz and ff = f.f;
+// b n_d n_i = b f_d f_i / ff = k (f2 / ff) f_d f_i with f2 = min(ff, 1), so
+// neither |f| nor a quotient by ff is needed unless a fallback state still has
+// |f| > 1 (then f2 / ff = 1 / ff; such waves take the branch).
 template <class R>
-__device__ __forceinline__ void eddington_row(R fx, R fy, R fz, R fn, int d, int closure, R& Tx, R& Ty, R& Tz,
+__device__ __forceinline__ void eddington_row(R fx, R fy, R fz, R ff, int d, int closure, R& Tx, R& Ty, R& Tz,
                                               R& Tdd) {
-  const R fh = rmin(fn, R(1));
-  const R chi = closure_chi(fh, closure);
-  const R a = R(0.5) * (R(1) - chi);
-  const R bb = R(0.5) * (R(3) * chi - R(1));
-  const bool has = fn > R(0);
-  const R inv = has ? R(1) / fn : R(0);
-  const R nx = fx * inv, ny = fy * inv, nz = fz * inv;
-  const R nd = d == 0 ? nx : (d == 1 ? ny : nz);
-  const R bn = has ? bb * nd : R(0);
-  Tx = bn * nx + (d == 0 ? a : R(0));
-  Ty = bn * ny + (d == 1 ? a : R(0));
-  Tz = bn * nz + (d == 2 ? a : R(0));
+  const R f2 = rmin(ff, R(1));
+  const R k = closure_k(f2, closure);
+  const R a = (R(1) - f2 * k) * R(1.0 / 3.0);
+  R g = k;
+  const bool over = ff > R(1);
+  if (__ballot(over)) g = over ? k / ff : k;
+  const R fd = d == 0 ? fx : (d == 1 ? fy : fz);
+  const R gd = g * fd;
+  Tx = gd * fx + (d == 0 ? a : R(0));
+  Ty = gd * fy + (d == 1 ? a : R(0));
+  Tz = gd * fz + (d == 2 ? a : R(0));
   Tdd = d == 0 ? Tx : (d == 1 ? Ty : Tz);
 }
 

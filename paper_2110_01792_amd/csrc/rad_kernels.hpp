@@ -43,16 +43,16 @@ struct RadStageArgs {
   double rw;               //   register weight: each face adds rw * dt_sub/2 * F
 };
 
-// HLL flux of (E, F) along axis d between face states (E, f), |f| = nL, nR
+// HLL flux of (E, F) along axis d between face states (E, f), f.f = ffL, ffR
 // (Section 2.2.2).  The wave speed chat max(sqrt(T_dd^L), sqrt(T_dd^R)) is
 // formed as chat sqrt(max(T_dd^L, T_dd^R)) (sqrt is monotone and correctly
 // rounded: the same value).
 template <class R>
-__device__ __forceinline__ void rad_flux(R EL, R fLx, R fLy, R fLz, R nL, R ER, R fRx, R fRy, R fRz, R nR, int d,
+__device__ __forceinline__ void rad_flux(R EL, R fLx, R fLy, R fLz, R ffL, R ER, R fRx, R fRy, R fRz, R ffR, int d,
                                          int closure, R c, R chat, R ratio, R cc, R eps, R* out) {
   R TLx, TLy, TLz, dL, TRx, TRy, TRz, dR;
-  eddington_row<R>(fLx, fLy, fLz, nL, d, closure, TLx, TLy, TLz, dL);
-  eddington_row<R>(fRx, fRy, fRz, nR, d, closure, TRx, TRy, TRz, dR);
+  eddington_row<R>(fLx, fLy, fLz, ffL, d, closure, TLx, TLy, TLz, dL);
+  eddington_row<R>(fRx, fRy, fRz, ffR, d, closure, TRx, TRy, TRz, dR);
   const R S = chat * sqrt(rmax(dL, dR));
   const R cEL = c * EL, cER = c * ER;
   const R FLx = cEL * fLx, FLy = cEL * fLy, FLz = cEL * fLz;
@@ -73,9 +73,9 @@ __device__ __forceinline__ void rad_flux(R EL, R fLx, R fLy, R fLz, R nL, R ER, 
 template <class R, class Cells>
 __device__ __forceinline__ void rad_face(const R* sl, const R* sr, const Cells& cells, R rhol, R rhor, R dxd,
                                          int d, const RadParamsDev& p, R c, R chat, R ratio, R cc, R* out) {
-  R nl = sqrt((sl[1] * sl[1] + sl[2] * sl[2]) + sl[3] * sl[3]);
-  R nr = sqrt((sr[1] * sr[1] + sr[2] * sr[2]) + sr[3] * sr[3]);
-  const bool fb = (nl > R(1)) || (nr > R(1));
+  R ffl = (sl[1] * sl[1] + sl[2] * sl[2]) + sl[3] * sl[3];  // f.f of each side
+  R ffr = (sr[1] * sr[1] + sr[2] * sr[2]) + sr[3] * sr[3];
+  const bool fb = f_above_one(ffl) || f_above_one(ffr);
   R L[4], Rr[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -84,8 +84,8 @@ __device__ __forceinline__ void rad_face(const R* sl, const R* sr, const Cells& 
   }
   if (fb) {
     cells(L, Rr);
-    nl = sqrt((L[1] * L[1] + L[2] * L[2]) + L[3] * L[3]);
-    nr = sqrt((Rr[1] * Rr[1] + Rr[2] * Rr[2]) + Rr[3] * Rr[3]);
+    ffl = (L[1] * L[1] + L[2] * L[2]) + L[3] * L[3];
+    ffr = (Rr[1] * Rr[1] + Rr[2] * Rr[2]) + Rr[3] * Rr[3];
   }
   R eps = R(1);
   if (p.tau_correction) {
@@ -95,7 +95,7 @@ __device__ __forceinline__ void rad_face(const R* sl, const R* sr, const Cells& 
     const bool thick = !fb && tau > R(1);
     if (__ballot(thick)) eps = thick ? R(1) / tau : R(1);
   }
-  rad_flux<R>(L[0], L[1], L[2], L[3], nl, Rr[0], Rr[1], Rr[2], Rr[3], nr, d, p.closure, c, chat, ratio, cc, eps, out);
+  rad_flux<R>(L[0], L[1], L[2], L[3], ffl, Rr[0], Rr[1], Rr[2], Rr[3], ffr, d, p.closure, c, chat, ratio, cc, eps, out);
 }
 
 // Matter-radiation coupling of one cell (Section 2.2.3), FP64 throughout.
