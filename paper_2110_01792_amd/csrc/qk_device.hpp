@@ -210,14 +210,24 @@ __device__ __forceinline__ float chi_tilde<float>(float pm2, float pm1, float pp
 //   1 Eddington, chi = 1/3: k = 0;
 //   2 Minerbo in the polynomial form chi = 1/3 + (2/15)(3 f^2 - f^3 + 3 f^4)
 //     (Cernohorsky & Bludman 1994): k = (3 - f + 3 f^2) / 5.
-// Then b = f2 k and a = (1 - b) / 3.  Levermore takes one quotient here,
-// where chi and b / |f|^2 took two, and b has no cancellation near f = 0.
-// The closure enters the flux only through this function.
+// Then b = f2 k and a = (1 - b) / 3.  The two states of one face share one
+// Levermore quotient, 3 / (2 + s_L) = 3 (2 + s_R) / ((2 + s_L)(2 + s_R))
+// with each 2 + s in [3, 4]: one quotient per face where chi and b / |f|^2
+// took two per state, and b has no cancellation near f = 0.  The closure
+// enters the flux only through k.
 template <class R>
-__device__ __forceinline__ R closure_k(R f2, int closure) {
-  if (closure == 1) return R(0);
-  if (closure == 2) return ((R(3) - sqrt(f2)) + R(3) * f2) * R(0.2);
-  return R(3) / (R(2) + sqrt(R(4) - R(3) * f2));
+__device__ __forceinline__ void closure_k2(R f2L, R f2R, int closure, R& kL, R& kR) {
+  if (closure == 1) {
+    kL = kR = R(0);
+  } else if (closure == 2) {
+    kL = ((R(3) - sqrt(f2L)) + R(3) * f2L) * R(0.2);
+    kR = ((R(3) - sqrt(f2R)) + R(3) * f2R) * R(0.2);
+  } else {
+    const R dl = R(2) + sqrt(R(4) - R(3) * f2L), dr = R(2) + sqrt(R(4) - R(3) * f2R);
+    const R q = R(3) / (dl * dr);
+    kL = q * dr;
+    kR = q * dl;
+  }
 }
 
 // |f| > 1 decided on ff = f.f: sqrt is monotone and correctly rounded, and
@@ -229,15 +239,14 @@ __device__ __forceinline__ bool f_above_one(R ff) {
 }
 
 // Row `d` of the Eddington tensor P/E; Tdd = P_dd/E (the HLL speed is
-// chat sqrt(Tdd)).  Cartesian components of f are fx, fy, fz and ff = f.f;
-// b n_d n_i = b f_d f_i / ff = k (f2 / ff) f_d f_i with f2 = min(ff, 1), so
-// neither |f| nor a quotient by ff is needed unless a fallback state still has
-// |f| > 1 (then f2 / ff = 1 / ff; such waves take the branch).
+// chat sqrt(Tdd)).  Cartesian components of f are fx, fy, fz, ff = f.f,
+// f2 = min(ff, 1) and k from closure_k2.  b n_d n_i = b f_d f_i / ff =
+// k (f2 / ff) f_d f_i, so neither |f| nor a quotient by ff is needed unless a
+// fallback state still has |f| > 1 (then f2 / ff = 1 / ff; such waves take
+// the branch).
 template <class R>
-__device__ __forceinline__ void eddington_row(R fx, R fy, R fz, R ff, int d, int closure, R& Tx, R& Ty, R& Tz,
+__device__ __forceinline__ void eddington_row(R fx, R fy, R fz, R ff, R f2, R k, int d, R& Tx, R& Ty, R& Tz,
                                               R& Tdd) {
-  const R f2 = rmin(ff, R(1));
-  const R k = closure_k(f2, closure);
   const R a = (R(1) - f2 * k) * R(1.0 / 3.0);
   R g = k;
   const bool over = ff > R(1);

@@ -50,9 +50,11 @@ struct RadStageArgs {
 template <class R>
 __device__ __forceinline__ void rad_flux(R EL, R fLx, R fLy, R fLz, R ffL, R ER, R fRx, R fRy, R fRz, R ffR, int d,
                                          int closure, R c, R chat, R ratio, R cc, R eps, R* out) {
-  R TLx, TLy, TLz, dL, TRx, TRy, TRz, dR;
-  eddington_row<R>(fLx, fLy, fLz, ffL, d, closure, TLx, TLy, TLz, dL);
-  eddington_row<R>(fRx, fRy, fRz, ffR, d, closure, TRx, TRy, TRz, dR);
+  R TLx, TLy, TLz, dL, TRx, TRy, TRz, dR, kL, kR;
+  const R f2L = rmin(ffL, R(1)), f2R = rmin(ffR, R(1));
+  closure_k2<R>(f2L, f2R, closure, kL, kR);
+  eddington_row<R>(fLx, fLy, fLz, ffL, f2L, kL, d, TLx, TLy, TLz, dL);
+  eddington_row<R>(fRx, fRy, fRz, ffR, f2R, kR, d, TRx, TRy, TRz, dR);
   const R S = chat * sqrt(rmax(dL, dR));
   const R cEL = c * EL, cER = c * ER;
   const R FLx = cEL * fLx, FLy = cEL * fLy, FLz = cEL * fLz;
@@ -101,13 +103,15 @@ __device__ __forceinline__ void rad_face(const R* sl, const R* sr, const Cells& 
 // Matter-radiation coupling of one cell (Section 2.2.3), FP64 throughout.
 // gas = (rho, mx, my, mz, E), rad = (E_r, Fx, Fy, Fz); S is the optional
 // radiation source added over dt; returns iterations used, sets *fail when the
-// iteration cap is reached.
+// iteration cap is reached.  Quotients by the same denominator (rho, the
+// Jacobian entry dF_G/dE_g, the flux factor) are taken once as a reciprocal.
 __device__ __forceinline__ int exchange(const RadParamsDev& p, double dt, double S, double* gas, double* rad,
                                         bool& fail) {
   const double rho = gas[0];
   const double c = p.c, ch = p.chat;
   const double coc = c / ch;
-  const double Ek0 = 0.5 * ((gas[1] * gas[1] + gas[2] * gas[2]) + gas[3] * gas[3]) / rho;
+  const double inv_rho = 1.0 / rho;
+  const double Ek0 = 0.5 * ((gas[1] * gas[1] + gas[2] * gas[2]) + gas[3] * gas[3]) * inv_rho;
   const double Eg0 = gas[4] - Ek0;
   const double Er0 = rad[0];
   const double Etot = Eg0 + coc * (Er0 + S);
@@ -116,7 +120,7 @@ __device__ __forceinline__ int exchange(const RadParamsDev& p, double dt, double
   const double dFG_dEr = -c * dt * rho * p.kappa_P;
   const double dFR_dEr = 1.0 + ch * dt * rho * p.kappa_P;
   const double gm1 = p.gamma - 1.0;
-  const double Tfac = gm1 / rho;                       // T = E_g (gamma-1)/rho
+  const double Tfac = gm1 * inv_rho;                   // T = E_g (gamma-1)/rho
   double Eg = Eg0, Er = Er0;
   int it = 0;
   bool conv = false;
@@ -140,23 +144,25 @@ __device__ __forceinline__ int exchange(const RadParamsDev& p, double dt, double
     }
     const double dFG_dEg = 1.0 + coc * dRdEg;
     const double dFR_dEg = -dRdEg;
-    const double eta = -dFR_dEg / dFG_dEg;
+    const double inv_g = 1.0 / dFG_dEg;
+    const double eta = -dFR_dEg * inv_g;
     const double dEr = -(FR + eta * FG) / (dFR_dEr + eta * dFG_dEr);
-    const double dEg = -(FG + dEr * dFG_dEr) / dFG_dEg;
+    const double dEg = -(FG + dEr * dFG_dEr) * inv_g;
     Eg += dEg;
     Er += dEr;
   }
   fail = fail || !conv;
-  const double fac = 1.0 + rho * p.kappa_R * ch * dt;
+  const double inv_fac = 1.0 / (1.0 + rho * p.kappa_R * ch * dt);
+  const double inv_cc = 1.0 / (ch * c);
   double m[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const double F0 = rad[1 + d];
-    const double F1 = F0 / fac;
-    m[d] = gas[1 + d] - (F1 - F0) / (ch * c);
+    const double F1 = F0 * inv_fac;
+    m[d] = gas[1 + d] - (F1 - F0) * inv_cc;
     rad[1 + d] = F1;
   }
-  const double Ek1 = 0.5 * ((m[0] * m[0] + m[1] * m[1]) + m[2] * m[2]) / rho;
+  const double Ek1 = 0.5 * ((m[0] * m[0] + m[1] * m[1]) + m[2] * m[2]) * inv_rho;
   const double dEk = Ek1 - Ek0;
   gas[1] = m[0];
   gas[2] = m[1];
