@@ -42,7 +42,7 @@ HYDRO_FLOPS_PER_CELL_STAGE = 45 * 15 + 106 * 3 + 13 + 57.5 + 11
 # The same runs give the stage's VALU issue rate (SQ_INSTS_VALU against 1024
 # SIMDs x 2.4 GHz / 4 cycles per wave64 instruction, mean of the two stages).
 STAGE_VALU_ISSUE_FRAC = 0.641
-STAGE_TRAFFIC = {"bytes_per_launch": 2.923e9, "sources_sha1": "60bdb2c515cc7a8251f5d53a4937a30beeaf8a6d"}
+STAGE_TRAFFIC = {"bytes_per_launch": 2.913e9, "sources_sha1": "04d0a3210e85a43359360a63a9849b6b49b7e947"}
 # The stage kernel's sources and its launch plan (the z-chunk length changes the traffic).
 KERNEL_SOURCES = ("paper_2110_01792_amd/csrc/hydro_kernels.hpp", "paper_2110_01792_amd/csrc/qk_device.hpp",
                   "paper_2110_01792_amd/csrc/api.hip")

@@ -169,12 +169,7 @@ __global__ __launch_bounds__(TX* TY) void batch_max_signal_kernel(const BatchBox
     for (int k = z0; k < z1; ++k) {
       double q[5];
       load_cons(bb.U, b.vs, cell(b, i, j, k), q);
-      const double ri = q[0];
-      const double ux = q[1] / ri, uy = q[2] / ri, uz = q[3] / ri;
-      const double ek = 0.5 * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]) / ri;
-      const double P = gm1 * (q[4] - ek);
-      m = fmax(m, sqrt((ux * ux + uy * uy) + uz * uz) + sqrt(g * P / ri));
-      bad = bad || !(ri > 0.0) || !(P > 0.0);
+      m = fmax(m, signal_speed(q, g, gm1, bad));
     }
   }
   if (bad) atomicOr(err, ERR_NEG);

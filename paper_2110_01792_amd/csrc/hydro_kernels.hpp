@@ -684,13 +684,7 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
         double q[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) q[v] = double(S(unew[v]));
-        const double ri = q[0];
-        const double ux = q[1] / ri, uy = q[2] / ri, uz = q[3] / ri;
-        const double ek = 0.5 * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]) / ri;
-        const double P = gm1 * (q[4] - ek);
-        const double s = sqrt((ux * ux + uy * uy) + uz * uz) + sqrt(a.gamma * P / ri);
-        smax = fmax(smax, s);
-        bad = bad || !(ri > 0.0) || !(P > 0.0);
+        smax = fmax(smax, signal_speed(q, a.gamma, gm1, bad));
       }
     }
   }
@@ -822,13 +816,7 @@ __global__ __launch_bounds__(NT) void max_signal_kernel(const S* __restrict__ U,
     const int k = (int)(c / ((int64_t)b.n0 * b.n1));
     double q[5];
     load_cons(U, b.vs, cell(b, i, j, k), q);
-    const double ri = q[0];
-    const double ux = q[1] / ri, uy = q[2] / ri, uz = q[3] / ri;
-    const double ek = 0.5 * ((q[1] * q[1] + q[2] * q[2]) + q[3] * q[3]) / ri;
-    const double P = gm1 * (q[4] - ek);
-    const double s = sqrt((ux * ux + uy * uy) + uz * uz) + sqrt(gamma * P / ri);
-    m = fmax(m, s);
-    bad = bad || !(ri > 0.0) || !(P > 0.0);
+    m = fmax(m, signal_speed(q, gamma, gm1, bad));
   }
   if (bad) atomicOr(err, ERR_NEG);
   block_max_to<NT>(m, smax);

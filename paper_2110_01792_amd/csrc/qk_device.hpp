@@ -120,15 +120,24 @@ __device__ __forceinline__ void hllc(const R* WL, const R* WR, const GasK<R>& k,
   const R rL = WL[0], uL = WL[1], vL = WL[2], wL = WL[3], pL = WL[4];
   const R rR = WR[0], uR = WR[1], vR = WR[2], wR = WR[3], pR = WR[4];
   const R g = k.g;
-  const R cL = sqrt(g * pL / rL);
-  const R cR = sqrt(g * pR / rR);
+  const R irL = R(1) / rL, irR = R(1) / rR;
+  const R cL = sqrt(g * pL * irL);
+  const R cR = sqrt(g * pR * irR);
   const R rbar = R(0.5) * (rL + rR);
   const R cbar = R(0.5) * (cL + cR);
   const R ps = rmax(R(0), R(0.5) * (pL + pR) - R(0.5) * (uR - uL) * rbar * cbar);
-  const R qL = (ps <= pL) ? R(1) : sqrt(R(1) + k.gq * (ps / pL - R(1)));
-  const R qR = (ps <= pR) ? R(1) : sqrt(R(1) + k.gq * (ps / pR - R(1)));
-  const R SL = uL - cL * qL;
-  const R SR = uR + cR * qR;
+  // S_L = u_L - c_L q_L with q_L = 1 if p* <= p_L, else sqrt(1 + gq (p*/p_L - 1));
+  // there c_L^2 q_L^2 = gamma (p_L + gq (p* - p_L)) / rho_L, so one square root
+  // with the side's reciprocal density gives c_L q_L (likewise on the right).
+  // Where the gas is at rest p* = p on both sides: whole waves skip the roots.
+  R aL = cL, aR = cR;
+  const bool shL = ps > pL, shR = ps > pR;
+  if (__ballot(shL || shR)) {
+    if (shL) aL = sqrt(g * (pL + k.gq * (ps - pL)) * irL);
+    if (shR) aR = sqrt(g * (pR + k.gq * (ps - pR)) * irR);
+  }
+  const R SL = uL - aL;
+  const R SR = uR + aR;
   const R Ss = ((pR - pL) + rL * uL * (SL - uL) - rR * uR * (SR - uR)) / (rL * (SL - uL) - rR * (SR - uR));
   // Side and branch exactly as the four-way selection on (S_L, S*, S_R):
   // 0 <= S_L: left flux; else 0 <= S*: left star; else 0 < S_R: right star;
@@ -139,14 +148,30 @@ __device__ __forceinline__ void hllc(const R* WL, const R* WR, const GasK<R>& k,
   const R p = left ? pL : pR, S = left ? SL : SR;
   const R E = p * k.inv_gm1 + R(0.5) * r * (u * u + (v * v + w * w));
   const R f0 = r * u, f1 = r * u * u + p, f2 = r * u * v, f3 = r * u * w, f4 = u * (E + p);
-  const R ph = (S - u) / (S - Ss);
+  // U*_4 = ph (E + (S* - u)(r S* + p / (S - u))) with ph = (S - u) / (S - S*);
+  // ph / (S - u) = 1 / (S - S*), so one reciprocal serves both quotients.
+  const R is = R(1) / (S - Ss);
+  const R ph = (S - u) * is;
   const R Us0 = ph * r, Us1 = ph * (r * Ss), Us2 = ph * (r * v), Us3 = ph * (r * w);
-  const R Us4 = ph * (E + (Ss - u) * (r * Ss + p / (S - u)));
+  const R Us4 = ph * (E + (Ss - u) * (r * Ss)) + (Ss - u) * (p * is);
   F[0] = star ? f0 + S * (Us0 - r) : f0;
   F[1] = star ? f1 + S * (Us1 - r * u) : f1;
   F[2] = star ? f2 + S * (Us2 - r * v) : f2;
   F[3] = star ? f3 + S * (Us3 - r * w) : f3;
   F[4] = star ? f4 + S * (Us4 - E) : f4;
+}
+
+// Signal speed |v| + c_s of one cell from its conserved state, in double
+// (Section 2.2.1, the CFL condition); sets bad where rho or P is not
+// positive.  One reciprocal of rho serves |v| = |m| / rho, the kinetic energy
+// and c_s^2 = gamma P / rho.  Every dt reduction uses this function.
+__device__ __forceinline__ double signal_speed(const double* q, double gamma, double gm1, bool& bad) {
+  const double rho = q[0];
+  const double inv = 1.0 / rho;
+  const double m2 = (q[1] * q[1] + q[2] * q[2]) + q[3] * q[3];
+  const double P = gm1 * (q[4] - 0.5 * m2 * inv);
+  bad = bad || !(rho > 0.0) || !(P > 0.0);
+  return sqrt(m2) * inv + sqrt(gamma * P * inv);
 }
 
 // Conserved -> primitive.  The internal energy E - |m|^2/(2 rho) is always
