@@ -256,6 +256,31 @@ def test_rhd_other_closures(ctx, closure):
     check_pair((g, r), (og, orr), b, f"closure {closure}")
 
 
+@pytest.mark.parametrize("closure", [0, 2])
+def test_rhd_streaming_states_take_the_fallback(ctx, closure):
+    """Reduced fluxes up to |f| = 0.97 in random directions, and 1 % of cells
+    at |f| = 1.03: reconstructed face states pass |f| = 1, so faces fall back
+    to the cell averages, and some of those averages still have |f| > 1 (the
+    closure then takes min(|f|, 1)).  One RHD step (10 substeps) against the
+    oracle.  (Eddington's closure cannot carry such streaming states: the
+    oracle itself reaches negative energies there.)"""
+    b, Ug, Ur, p = inputs.rhd_lognormal(n=24, seed=46)
+    rng = np.random.default_rng(47)
+    I = b.interior()
+    shape = (b.n[2], b.n[1], b.n[0])
+    d = rng.normal(size=(3,) + shape)
+    d /= np.linalg.norm(d, axis=0)
+    mag = rng.uniform(0.0, 0.97, size=shape)
+    mag[rng.uniform(size=shape) < 0.01] = 1.03
+    Ur[(slice(1, 4),) + I[1:]] = d * mag * p["c"] * Ur[(0,) + I[1:]]
+    p = dict(p, closure=closure)
+    g, r, st = gpu_rhd(ctx, b, Ug, Ur, p)
+    assert st == qb.QK_OK
+    og, orr, ost = oracle_rhd(b, Ug, Ur, p)
+    assert ost["neg_cells"] == 0 and ost["newton_fail"] == 0
+    check_pair((g, r), (og, orr), b, f"streaming, closure {closure}")
+
+
 def test_rhd_padded_layout_equals_contiguous_bitwise(ctx):
     """Gas and radiation states in one padded layout (shared pitches) give the
     bits of the contiguous layout over an RHD step; states of one box in
