@@ -167,11 +167,14 @@ qk_status quokka_batch_step(qk_ctx* ctx, const qk_box* boxes, int32_t nbox, void
                             const qk_rad_params* rp, double* dt_host, void* stream);
 
 /* Tile family (8: 8 x 8 columns; 16: 16 x 16; 14: 16 x 14 with separate x
- * and y sweep buffers), z-chunk length and autotuning time (ms per candidate
- * stage) chosen for the last batch step.  The autotuner times the
- * side-effect-free first stages of each candidate on the caller's boxes the
- * first time a box-shape signature is seen; results persist in the JSON file
- * named by the environment variable QK_TUNE_CACHE, if set. */
+ * and y sweep buffers) and z-chunk length chosen for the last batch step, and
+ * the autotuner's score of that choice (ms; 0 when the choice came from the
+ * cache).  The autotuner times the side-effect-free first stages of each
+ * candidate on the caller's boxes the first time a box-shape signature is
+ * seen, and scores it as hydro first stage + nsub_max x radiation first stage
+ * (the weights of a level step), each the fastest of three runs; results
+ * persist in the JSON file named by the environment variable QK_TUNE_CACHE,
+ * if set. */
 qk_status quokka_batch_config(qk_ctx* ctx, int32_t* tile, int32_t* zc, double* tune_ms);
 
 /* ------------------------------------------------------------------------
