@@ -248,3 +248,46 @@ def test_padded_layout_equals_contiguous_bitwise(ctx):
     assert ctx.sync_status() == qb.QK_OK
     assert np.array_equal(host(A), host(B.contiguous()))
     assert qb._check_state(B, b, 5) == (B.stride(2), B.stride(1), B.stride(0))
+
+
+def test_offsets_beyond_2_31_equal_a_small_box(ctx):
+    """A 784^3 box: each gas variable holds 792^3 = 4.97e8 elements, so the
+    element offsets of the last variables pass 2^31.  A uniform periodic state
+    with a seeded blob near the far corner, two steps at a fixed dt: the 64^3
+    region around the blob equals, bit for bit, the same blob in a small
+    periodic box (translation invariance: every face sees the same operands;
+    the blob's domain of dependence, 4 cells per stage, stays inside the
+    region), and the small box matches the oracle."""
+    import torch
+    N, m, h, gamma, dt = 784, 64, 1.0 / 256, 1.4, 0.1 / 256
+    small = inputs.make_box(m, L=m * h)
+    big = inputs.make_box(N, L=N * h)
+    assert 5 * int(np.prod(big.shape)) > 2 ** 31
+    rng = np.random.default_rng(61)
+    U = np.zeros((5,) + small.shape)
+    U[0] = 1.0
+    U[4] = 1.0 / (gamma - 1.0)
+    c = slice(small.ng + m // 2 - 3, small.ng + m // 2 + 3)
+    U[0, c, c, c] += rng.uniform(-0.2, 0.2, (6, 6, 6))
+    U[1:4, c, c, c] = rng.uniform(-0.1, 0.1, (3, 6, 6, 6))
+    U[4, c, c, c] += rng.uniform(-0.3, 0.3, (6, 6, 6))
+    gs = gpu_steps(ctx, small, U, gamma, 0.3, 2, dt=dt)
+    check(gs, oracle_steps(small, U, gamma, 0.3, 2, dt=dt), small, what="small box")
+
+    o = big.ng + N - m - 8  # region start in the big array (interior offset N - m - 8)
+    r = slice(o, o + m)
+    Ub = torch.empty((5,) + big.shape, dtype=torch.float64, device="cuda")
+    Ub[0].fill_(1.0)
+    Ub[1:4].zero_()
+    Ub[4].fill_(1.0 / (gamma - 1.0))
+    Ub[:, r, r, r] = torch.from_numpy(np.ascontiguousarray(U[small.interior()])).cuda()
+    ctx.fill_ghosts(big, Ub)
+    hp = qb.hydro_params(gamma, 0.3)
+    for _ in range(2):
+        ctx.hydro_step(big, Ub, hp, dt=dt)
+    assert ctx.sync_status() == qb.QK_OK
+    gb = Ub[:, r, r, r].cpu().numpy()
+    far = float(Ub[4, -big.ng - 1, -big.ng - 1, -big.ng - 1])
+    del Ub
+    assert np.array_equal(gb, gs[small.interior()])
+    assert far == 1.0 / (gamma - 1.0)
