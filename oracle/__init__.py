@@ -7,7 +7,8 @@ GPU path: the C source is oracle/quokka_oracle.c, loaded here with ctypes.
 
 Arrays are numpy float64, C-contiguous, shape (nvar, nz+2ng, ny+2ng, nx+2ng).
 A box is any object with attributes n (nx, ny, nz), ng, dx (3 floats) and
-bc ((lo, hi) per axis, 0 periodic, 1 outflow, 2 fixed).
+bc ((lo, hi) per axis, 0 periodic, 1 outflow, 2 fixed, 3 fixed with a
+zero-gradient radiation flux).
 
 Functions that no independent check fixes are marked "parity unpinned" in
 their docstring (see the test files for the pins of the others).
@@ -42,7 +43,8 @@ class _Region(ctypes.Structure):
 
 class _Stats(ctypes.Structure):
     _fields_ = [("neg_cells", ctypes.c_int64), ("newton_fail", ctypes.c_int64),
-                ("newton_iter_max", ctypes.c_int64), ("nsub", ctypes.c_int32), ("dt", ctypes.c_double)]
+                ("newton_iter_max", ctypes.c_int64), ("nsub", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("causal_cells", ctypes.c_int64)]
 
 
 _D = ctypes.POINTER(ctypes.c_double)
@@ -65,6 +67,7 @@ def _load():
                                      P(_Stats)]),
         "oracle_rad_rhs": (None, [P(_Box), _D, _D, P(_Rad), _D, P(_Stats)]),
         "oracle_rad_transport_substep": (None, [P(_Box), _D, _D, P(_Rad), ctypes.c_double, P(_Stats)]),
+        "oracle_rad_stage": (None, [P(_Box), _D, _D, _D, P(_Rad), ctypes.c_double, _D, P(_Stats)]),
         "oracle_exchange_cell": (ctypes.c_int, [P(_Rad), ctypes.c_double, ctypes.c_double, _D, _D, P(ctypes.c_int)]),
         "oracle_exchange_all": (None, [P(_Box), _D, _D, P(_Rad), ctypes.c_double, P(_Stats)]),
         "oracle_hydro_step_reg": (None, [P(_Box), _D, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -133,7 +136,7 @@ def _check(b, a, nvar):
 
 def _stats(st):
     return {"neg_cells": st.neg_cells, "newton_fail": st.newton_fail, "newton_iter_max": st.newton_iter_max,
-            "nsub": st.nsub, "dt": st.dt}
+            "nsub": st.nsub, "dt": st.dt, "causal_cells": st.causal_cells}
 
 
 def set_threads(n=0):
@@ -188,6 +191,20 @@ def rad_transport_substep(b, Ur, Ug, p, dt):
     _load().oracle_rad_transport_substep(ctypes.byref(_box(b)), _ptr(Ur), _ptr(Ug), ctypes.byref(_rad(p)),
                                          float(dt), ctypes.byref(st))
     return _stats(st)
+
+
+def rad_stage(b, Uin, Ug, p, dt, Ubase=None):
+    """One radiation RK stage: Uin + dt L(Uin) (first stage) or, given Ubase,
+    Ubase/2 + (Uin + dt L(Uin))/2; returns (Uout, stats).  Uout's ghosts are
+    those of Ubase (else Uin).  tau_correction 1 applies the causality rule of
+    Section 2.2.2, 2 the optical-depth factor without it."""
+    _check(b, Uin, 4)
+    _check(b, Ug, 5)
+    out = (Ubase if Ubase is not None else Uin).copy()
+    st = _Stats()
+    _load().oracle_rad_stage(ctypes.byref(_box(b)), _ptr(Uin), _ptr(Ubase) if Ubase is not None else ctypes.cast(None, _D),
+                             _ptr(Ug), ctypes.byref(_rad(p)), float(dt), _ptr(out), ctypes.byref(st))
+    return out, _stats(st)
 
 
 def exchange_cell(p, dt, gas, rad, S=0.0):

@@ -44,7 +44,7 @@ static geo make_geo(const ob_box* b) {
   for (int d = 0; d < 3; ++d) {
     g.n[d] = b->n[d];
     g.N[d] = b->n[d] + 2 * b->ng;
-    g.act[d] = !(b->n[d] == 1 && b->bc[d][0] != OB_FIXED && b->bc[d][1] != OB_FIXED);
+    g.act[d] = !(b->n[d] == 1 && b->bc[d][0] < OB_FIXED && b->bc[d][1] < OB_FIXED);
     g.lo[d] = g.act[d] ? -b->ng : 0;
     g.hi[d] = g.act[d] ? b->n[d] + b->ng : b->n[d];
   }
@@ -75,9 +75,11 @@ int oracle_set_threads(int n) {
 /* ------------------------------------------------------------------------ */
 /* boundary conditions: periodic wrap, zero-gradient outflow, fixed          */
 /* Filled axis by axis (x, then y over the full x extent, then z over the    */
-/* full x-y extent), which also fills edges and corners.                     */
+/* full x-y extent), which also fills edges and corners.  A fixed face with  */
+/* a free radiation flux acts as outflow for F_x, F_y, F_z of a radiation     */
+/* state (4 variables) and as fixed everywhere else.                          */
 /* ------------------------------------------------------------------------ */
-static int src_index(int i, int n, int ng, int bclo, int bchi) {
+static int src_index(int i, int n, int bclo, int bchi) {
   if (i < 0) {
     if (bclo == OB_PERIODIC) return ((i % n) + n) % n;
     if (bclo == OB_OUTFLOW) return 0;
@@ -88,8 +90,12 @@ static int src_index(int i, int n, int ng, int bclo, int bchi) {
     if (bchi == OB_OUTFLOW) return n - 1;
     return i;
   }
-  (void)ng;
   return i;
+}
+
+static int kind_for(int kind, int v, int nvar) {
+  if (kind != OB_FIXED_FREE_FLUX) return kind;
+  return (nvar == 4 && v >= 1) ? OB_OUTFLOW : OB_FIXED;
 }
 
 void oracle_fill_ghosts(const ob_box* b, double* U, int nvar) {
@@ -97,26 +103,31 @@ void oracle_fill_ghosts(const ob_box* b, double* U, int nvar) {
   const int ng = g.ng;
   for (int v = 0; v < nvar; ++v) {
     double* q = U + (size_t)v * g.vs;
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = kind_for(b->bc[d][0], v, nvar);
+      hi[d] = kind_for(b->bc[d][1], v, nvar);
+    }
     /* x */
     for (int k = 0; k < g.n[2]; ++k)
       for (int j = 0; j < g.n[1]; ++j)
         for (int i = -ng; i < g.n[0] + ng; ++i) {
           if (i >= 0 && i < g.n[0]) continue;
-          int s = src_index(i, g.n[0], ng, b->bc[0][0], b->bc[0][1]);
+          int s = src_index(i, g.n[0], lo[0], hi[0]);
           if (s != i) q[IX(&g, i, j, k)] = q[IX(&g, s, j, k)];
         }
     /* y, over full x extent */
     for (int k = 0; k < g.n[2]; ++k)
       for (int j = -ng; j < g.n[1] + ng; ++j) {
         if (j >= 0 && j < g.n[1]) continue;
-        int s = src_index(j, g.n[1], ng, b->bc[1][0], b->bc[1][1]);
+        int s = src_index(j, g.n[1], lo[1], hi[1]);
         if (s == j) continue;
         for (int i = -ng; i < g.n[0] + ng; ++i) q[IX(&g, i, j, k)] = q[IX(&g, i, s, k)];
       }
     /* z, over full x-y extent */
     for (int k = -ng; k < g.n[2] + ng; ++k) {
       if (k >= 0 && k < g.n[2]) continue;
-      int s = src_index(k, g.n[2], ng, b->bc[2][0], b->bc[2][1]);
+      int s = src_index(k, g.n[2], lo[2], hi[2]);
       if (s == k) continue;
       for (int j = -ng; j < g.n[1] + ng; ++j)
         for (int i = -ng; i < g.n[0] + ng; ++i) q[IX(&g, i, j, k)] = q[IX(&g, i, j, s)];
@@ -691,24 +702,20 @@ void oracle_hll_rad(double EL, const double FL[3], double ER, const double FR[3]
   for (int n = 0; n < 4; ++n) flux[n] = 0.5 * (phL[n] + phR[n]) - 0.5 * eps * S * (UR[n] - UL[n]);
 }
 
-/* Radiation transport right-hand side (Section 2.2.2): PPM (no flattening)
- * of E_r and the reduced flux f = F/(c E_r); per-face first-order fallback
- * when either reconstructed |f| exceeds 1; closure; HLL; unsplit divergence. */
-static void rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const ob_rad* p, double* L, ob_stats* st,
-                    const ob_region* r, double* reg, double w);
-
-void oracle_rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const ob_rad* p, double* L, ob_stats* st) {
-  rad_rhs(b, Ur, Ug, p, L, st, NULL, NULL, 0.0);
-}
-
-static void rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const ob_rad* p, double* L, ob_stats* st,
-                    const ob_region* r, double* reg, double w) {
+/* Radiation face fluxes of one stage input (Section 2.2.2): PPM (no
+ * flattening) of E_r and the reduced flux f = F/(c E_r); per-face first-order
+ * fallback when either reconstructed |f| exceeds 1; closure; HLL.  Fc[d]
+ * carries the optical-depth factor eps = min(1, 1/tau), tau = dx kappa_R
+ * (rho_L + rho_R)/2 (the paper names the correction, not its formula: a
+ * reading); Fu[d] is the same flux with eps = 1.  The two are equal (the same
+ * bits) at faces with tau <= 1 or with the correction off.  Fu may be NULL. */
+static void rad_faces(const ob_box* b, const double* Ur, const double* Ug, const ob_rad* p, double* Fc, double* Fu,
+                      ob_stats* st) {
   geo g = make_geo(b);
   const size_t vs = g.vs;
   double* Q = (double*)malloc(4 * vs * sizeof(double));
   double* aL = (double*)malloc(4 * vs * sizeof(double));
   double* aR = (double*)malloc(4 * vs * sizeof(double));
-  double* Fd = (double*)malloc(3 * 4 * vs * sizeof(double));
   const double c = p->c;
   int64_t neg = 0;
 
@@ -724,8 +731,9 @@ static void rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const o
         if (!(Ur[IX(&g, i, j, k)] > 0.0)) ++neg;
 
   for (int d = 0; d < 3; ++d) {
-    double* F = Fd + (size_t)d * 4 * vs;
     if (!g.act[d]) continue;
+    double* F = Fc + (size_t)d * 4 * vs;
+    double* G = Fu ? Fu + (size_t)d * 4 * vs : NULL;
     const ptrdiff_t s = g.st[d];
     int lo[3] = {0, 0, 0}, hi[3] = {g.n[0], g.n[1], g.n[2]};
     lo[d] = -1;
@@ -748,8 +756,7 @@ static void rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const o
       const double nL = sqrt((fL[0] * fL[0] + fL[1] * fL[1]) + fL[2] * fL[2]);
       const double nR = sqrt((fR[0] * fR[0] + fR[1] * fR[1]) + fR[2] * fR[2]);
       double FLv[3], FRv[3];
-      const int fallback = (nL > 1.0) || (nR > 1.0);
-      if (fallback) {
+      if ((nL > 1.0) || (nR > 1.0)) {
         EL = Ur[ol];
         ER = Ur[o];
         for (int m = 0; m < 3; ++m) {
@@ -762,19 +769,30 @@ static void rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const o
           FRv[m] = c * ER * fR[m];
         }
       }
-      /* optical-depth factor: the paper gives its purpose, not its formula
-         (a reading; parity partly pinned by the radiation pressure tube) */
       double eps = 1.0;
-      if (p->tau_correction && !fallback) {
+      if (p->tau_correction) {
         const double tau = b->dx[d] * p->kappa_R * (0.5 * (Ug[ol] + Ug[o]));
         eps = fmin(1.0, 1.0 / tau);
       }
       double f[4];
       oracle_hll_rad(EL, FLv, ER, FRv, d, p, eps, f);
       for (int v = 0; v < 4; ++v) F[v * vs + o] = f[v];
+      if (G) {
+        oracle_hll_rad(EL, FLv, ER, FRv, d, p, 1.0, f);
+        for (int v = 0; v < 4; ++v) G[v * vs + o] = f[v];
+      }
     }
   }
+  if (st) st->neg_cells += neg;
+  free(Q);
+  free(aL);
+  free(aR);
+}
 
+/* Unsplit divergence L = -((dF_x/dx + dF_y/dy) + dF_z/dz) of 4 variables. */
+static void rad_divergence(const ob_box* b, const double* Fd, double* L) {
+  geo g = make_geo(b);
+  const size_t vs = g.vs;
   LOOP3(0, g.n[2], 0, g.n[1], 0, g.n[0]) {
     const size_t o = IX(&g, i, j, k);
     for (int v = 0; v < 4; ++v) {
@@ -790,12 +808,104 @@ static void rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const o
       L[v * vs + o] = -((t[0] + t[1]) + t[2]);
     }
   }
-  if (reg) record_region(&g, Fd, 4, r, reg, w);
-  if (st) st->neg_cells += neg;
-  free(Q);
-  free(aL);
-  free(aR);
+}
+
+/* Right-hand side of the radiation transport with the optical-depth factor as
+ * given (no state is formed, so the causality rule of the stage does not enter). */
+void oracle_rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const ob_rad* p, double* L, ob_stats* st) {
+  geo g = make_geo(b);
+  double* Fd = (double*)calloc(3 * 4 * g.vs, sizeof(double));
+  rad_faces(b, Ur, Ug, p, Fd, NULL, st);
+  rad_divergence(b, Fd, L);
   free(Fd);
+}
+
+/* One radiation RK stage (Section 2.2.2): Uout = Uin + dt L(Uin) (Ubase NULL,
+ * first stage) or Uout = Ubase/2 + (Uin + dt L(Uin))/2 (second stage), over
+ * interior cells.
+ * Causality rule: the optical-depth correction is disabled for the cells
+ * where it produces a causality-violating state.  Reading: the stage is
+ * formed with the corrected fluxes; every interior cell whose resulting state
+ * has |F| > c E_r is a violating cell; at every face of a violating cell the
+ * uncorrected flux replaces the corrected one (a face is one flux for both of
+ * its cells, so the update stays conservative) and the stage is formed again
+ * from the stage input.  One pass; ghost cells are never updated, so they
+ * never violate.  The faces used are recorded in the region register. */
+static void rad_stage(const ob_box* b, const double* Uin, const double* Ubase, const double* Ug, const ob_rad* p,
+                      double dt, double* Uout, const ob_region* r, double* reg, double w, ob_stats* st) {
+  geo g = make_geo(b);
+  const size_t vs = g.vs;
+  double* Fc = (double*)calloc(3 * 4 * vs, sizeof(double));
+  /* tau_correction 1: the correction with the causality rule; 2: the correction
+     everywhere (no rule; for comparison) */
+  double* Fu = (p->tau_correction == 1) ? (double*)calloc(3 * 4 * vs, sizeof(double)) : NULL;
+  double* L = (double*)calloc(4 * vs, sizeof(double));
+  rad_faces(b, Uin, Ug, p, Fc, Fu, st);
+  rad_divergence(b, Fc, L);
+  if (Ubase) {
+    memcpy(Uout, Ubase, 4 * vs * sizeof(double));
+    rk2_interior(&g, 4, Uout, Uin, L, dt);
+  } else {
+    euler_interior(&g, 4, Uin, Uout, L, dt);
+  }
+  if (Fu) {
+    double* viol = (double*)calloc(vs, sizeof(double));
+    int64_t nviol = 0;
+    for (int k = 0; k < g.n[2]; ++k)
+      for (int j = 0; j < g.n[1]; ++j)
+        for (int i = 0; i < g.n[0]; ++i) {
+          const size_t o = IX(&g, i, j, k);
+          const double Fx = Uout[vs + o], Fy = Uout[2 * vs + o], Fz = Uout[3 * vs + o];
+          if (sqrt((Fx * Fx + Fy * Fy) + Fz * Fz) > p->c * Uout[o]) {
+            viol[o] = 1.0;
+            ++nviol;
+          }
+        }
+    if (nviol > 0) {
+      /* a ghost cell across a periodic boundary is its image's cell, so a face
+         there is switched with the face it repeats; other ghosts never violate */
+      ob_box bp = *b;
+      for (int d = 0; d < 3; ++d)
+        for (int t = 0; t < 2; ++t)
+          if (bp.bc[d][t] != OB_PERIODIC) bp.bc[d][t] = OB_FIXED;
+      oracle_fill_ghosts(&bp, viol, 1);
+      /* face between cells o - st[d] and o along d: uncorrected if either violates */
+      for (int d = 0; d < 3; ++d) {
+        if (!g.act[d]) continue;
+        const ptrdiff_t s = g.st[d];
+        int hi2[3] = {g.n[0], g.n[1], g.n[2]};
+        hi2[d] = g.n[d] + 1;
+        for (int k = 0; k < hi2[2]; ++k)
+          for (int j = 0; j < hi2[1]; ++j)
+            for (int i = 0; i < hi2[0]; ++i) {
+              const size_t o = IX(&g, i, j, k);
+              if (viol[o] != 0.0 || viol[o - s] != 0.0)
+                for (int v = 0; v < 4; ++v) {
+                  const size_t q = (size_t)d * 4 * vs + v * vs + o;
+                  Fc[q] = Fu[q];
+                }
+            }
+      }
+      rad_divergence(b, Fc, L);
+      if (Ubase) {
+        memcpy(Uout, Ubase, 4 * vs * sizeof(double));
+        rk2_interior(&g, 4, Uout, Uin, L, dt);
+      } else {
+        euler_interior(&g, 4, Uin, Uout, L, dt);
+      }
+      if (st) st->causal_cells += nviol;
+    }
+    free(viol);
+  }
+  if (reg) record_region(&g, Fc, 4, r, reg, w);
+  free(Fc);
+  free(Fu);
+  free(L);
+}
+
+void oracle_rad_stage(const ob_box* b, const double* Uin, const double* Ubase, const double* Ug, const ob_rad* p,
+                      double dt, double* Uout, ob_stats* st) {
+  rad_stage(b, Uin, Ubase, Ug, p, dt, Uout, NULL, NULL, 0.0, st);
 }
 
 void oracle_rad_transport_substep(const ob_box* b, double* Ur, const double* Ug, const ob_rad* p, double dt,
@@ -808,16 +918,15 @@ void oracle_rad_transport_substep_reg(const ob_box* b, double* Ur, const double*
   geo g = make_geo(b);
   const size_t nb = 4 * g.vs * sizeof(double);
   double* U1 = (double*)malloc(nb);
-  double* Lb = (double*)calloc(4 * g.vs, sizeof(double));
-  memcpy(U1, Ur, nb);
-  rad_rhs(b, Ur, Ug, p, Lb, st, r, reg, 0.5 * dt * weight);
-  euler_interior(&g, 4, Ur, U1, Lb, dt);
+  double* U2 = (double*)malloc(nb);
+  memcpy(U1, Ur, nb); /* fixed ghosts of the stage state equal those of Ur */
+  rad_stage(b, Ur, NULL, Ug, p, dt, U1, r, reg, 0.5 * dt * weight, st);
   oracle_fill_ghosts(b, U1, 4);
-  rad_rhs(b, U1, Ug, p, Lb, st, r, reg, 0.5 * dt * weight);
-  rk2_interior(&g, 4, Ur, U1, Lb, dt);
+  rad_stage(b, U1, Ur, Ug, p, dt, U2, r, reg, 0.5 * dt * weight, st);
+  memcpy(Ur, U2, nb);
   oracle_fill_ghosts(b, Ur, 4);
   free(U1);
-  free(Lb);
+  free(U2);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -12,7 +12,9 @@
  * paper's printed results or exact solutions.  One part is only partly
  * pinned: the optical-depth factor of the radiation HLL flux, whose formula
  * the paper does not give (its value is a reading; the radiation pressure
- * tube runs with it active and holds the paper's accuracy in its interior).
+ * tube of Section 3.3.1 runs with it active and holds the paper's 0.2 per
+ * cent over the whole column; the causality rule that disables it is pinned
+ * by its defining properties).
  *
  * Array layout used by every entry point: one contiguous float64 array per
  * state, shape (nvar, nz+2ng, ny+2ng, nx+2ng), x fastest.  Gas state has
@@ -27,7 +29,10 @@
 extern "C" {
 #endif
 
-enum { OB_PERIODIC = 0, OB_OUTFLOW = 1, OB_FIXED = 2 };
+/* Boundary kinds.  OB_FIXED_FREE_FLUX: Dirichlet ghosts (held as given, like
+ * OB_FIXED) except the radiation flux F_x, F_y, F_z of a radiation state
+ * (4 variables), whose ghosts are zero-gradient copies (like OB_OUTFLOW). */
+enum { OB_PERIODIC = 0, OB_OUTFLOW = 1, OB_FIXED = 2, OB_FIXED_FREE_FLUX = 3 };
 
 typedef struct {
   int32_t n[3];      /* interior cells per axis */
@@ -42,7 +47,10 @@ typedef struct {
   const double* src;  /* NULL, or the radiation energy source rate j per cell (one variable
                          in the box layout); the coupling adds S = dt j (Section 2.2.3) */
 } ob_rad;   /* closure: 0 Levermore, 1 Eddington, 2 Minerbo.  eos: 0 ideal (P = rho T),
-               1 E_g = alpha T^4 / 4.  recon: 0 PPM, 1 PLM (hydro and radiation). */
+               1 E_g = alpha T^4 / 4.  recon: 0 PPM, 1 PLM (hydro and radiation).
+               tau_correction: 0 off; 1 the optical-depth factor with the
+               causality rule of Section 2.2.2; 2 the factor everywhere
+               (no rule; for comparison). */
 
 /* Result counters returned by the step drivers. */
 typedef struct {
@@ -51,6 +59,8 @@ typedef struct {
   int64_t newton_iter_max;/* largest iteration count of any cell */
   int32_t nsub;           /* radiation substeps taken */
   double dt;              /* hydro step actually taken */
+  int64_t causal_cells;   /* radiation stage updates redone without the optical-depth
+                             correction at their faces (|F| > c E_r; Section 2.2.2) */
 } ob_stats;
 
 void   oracle_fill_ghosts(const ob_box* b, double* U, int nvar);
@@ -60,6 +70,12 @@ void   oracle_hydro_step(const ob_box* b, double* U, double gamma, double cfl, d
                          ob_stats* st);
 void   oracle_rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const ob_rad* p, double* L, ob_stats* st);
 void   oracle_rad_transport_substep(const ob_box* b, double* Ur, const double* Ug, const ob_rad* p, double dt, ob_stats* st);
+/* One radiation RK stage over interior cells: Uout = Uin + dt L(Uin) if Ubase
+ * is NULL, else Uout = Ubase/2 + (Uin + dt L(Uin))/2; Uout's ghosts are left
+ * as they are.  With tau_correction == 1 the causality rule of Section 2.2.2
+ * applies (see rad_stage). */
+void   oracle_rad_stage(const ob_box* b, const double* Uin, const double* Ubase, const double* Ug, const ob_rad* p,
+                        double dt, double* Uout, ob_stats* st);
 int    oracle_exchange_cell(const ob_rad* p, double dt, double S, double* rho_m_E /*5*/, double* Er_F /*4*/,
                             int* iters);
 void   oracle_exchange_all(const ob_box* b, double* Ug, double* Ur, const ob_rad* p, double dt, ob_stats* st);

@@ -19,7 +19,9 @@ from typing import NamedTuple, Optional, Sequence, Tuple
 
 import numpy as np
 
-PERIODIC, OUTFLOW, FIXED = 0, 1, 2
+# FIXED_FREE_FLUX: Dirichlet ghosts except the radiation flux of a radiation
+# state, which is zero-gradient (see rad_pressure_tube)
+PERIODIC, OUTFLOW, FIXED, FIXED_FREE_FLUX = 0, 1, 2, 3
 
 
 class Box(NamedTuple):
@@ -236,7 +238,10 @@ def batch_level(nbox=600, seed=5, gamma=5.0 / 3.0, ng=4, edges: Optional[Sequenc
 # [0, 128] cm, 128 cells, in which radiation and gas pressure gradients balance
 # in the equilibrium-diffusion regime (tau_cell ~ 100).  cgs, mu = 2.33 m_H,
 # gamma 5/3, kappa_P = kappa_R = 100, T_0 = 2.75e7 K, rho_0 = 1,
-# drho/dx(0) = 0.005; chat = 10 c_s(0); Dirichlet (fixed) ends.
+# drho/dx(0) = 0.005; chat = 10 c_s(0).  Dirichlet ends hold what the ODE
+# solution fixes (rho, v = 0, T and so E_gas and E_r = a_r T^4); the radiation
+# flux in the ghost cells is not given by it and is extrapolated with zero
+# gradient (boundary kind FIXED_FREE_FLUX).
 #
 # The update's EOS is P = rho T, so temperature is carried as T' = k_B T / mu
 # (erg/g) with a_r' = a_r (mu / k_B)^4, which leaves a_r T^4 and P unchanged.
@@ -275,7 +280,7 @@ def rad_pressure_tube(n=128, ng=4, L=128.0):
     T0, rho0, drho0 = 2.75e7 * kB_mu, 1.0, 0.005
     dT0 = -drho0 * T0 / (rho0 + (4.0 / 3.0) * a_r * T0 ** 3)
     dx = L / n
-    b = Box((n, 1, 1), ng, (dx, dx, dx), ((FIXED, FIXED), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC)))
+    b = Box((n, 1, 1), ng, (dx, dx, dx), ((FIXED_FREE_FLUX, FIXED_FREE_FLUX), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC)))
     xs = (np.arange(-ng, n + ng) + 0.5) * dx
     prof = np.zeros((len(xs), 3))
     y0 = np.array([rho0, T0, dT0])
@@ -300,6 +305,47 @@ def rad_pressure_tube(n=128, ng=4, L=128.0):
     p = rad_params(10.0 * cs0, gamma=gamma, c=CGS["c"], a_r=a_r, kappa_P=kappa, kappa_R=kappa, cfl=0.4,
                    newton_tol=1e-12, tau_correction=1)
     return b, Ug, Ur, p, {"T": T, "rho": rho, "t_end": L / cs0, "cfl": 0.4, "cs0": cs0}
+
+
+# ---------------------------------------------------------------------------
+# Streaming radiation entering an optically thick slab (Section 2.2.2: the
+# optical-depth correction can give |F| > c E_r where a streaming flux meets
+# a discontinuity between optically thin and thick cells).  Box n (x outflow,
+# y and z periodic), [0,1] along x, cubic cells; dimensionless units (c =
+# 1000, chat = 100, a_r = 1, kappa_R = 1 and kappa_P = 0 (a purely scattering
+# slab keeps its low E_r), gamma 5/3, P = rho T).
+# Thin cells (x below the interface) have rho dx = tau_thin, E_r = 1 and a
+# beam F = f_beam c E_r along a direction tilted in x-y by a seeded angle in
+# [-0.2, 0.2] rad; thick cells have rho dx = tau_thick, E_r = e_thick, F = 0.
+# The interface is x = 1/2 + 0.1 sin(2 pi (y + phi_y)) sin(2 pi (z + phi_z))
+# with seeded phases (so y and z faces also join thin and thick cells); v = 0
+# and the gas pressure uniform (T = 1 in thin cells, tau_thin/tau_thick in
+# thick ones).  Draws: angle, phi_y, phi_z.
+# ---------------------------------------------------------------------------
+def rad_thick_streaming(n=(32, 1, 1), seed=9, tau_thin=0.01, tau_thick=100.0, e_thick=1e-3, f_beam=0.99, ng=4):
+    if isinstance(n, int):
+        n = (n, n, n)
+    dx = 1.0 / n[0]
+    b = Box(tuple(int(v) for v in n), ng, (dx, dx, dx), ((OUTFLOW, OUTFLOW), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC)))
+    rng = np.random.default_rng(seed)
+    ang = rng.uniform(-0.2, 0.2)
+    phy, phz = rng.uniform(0.0, 1.0, 2)
+    z, y, x = cell_centres(b, with_ghosts=True)
+    xs = 0.5 + 0.1 * np.sin(2 * np.pi * (y + phy)) * np.sin(2 * np.pi * (z + phz))
+    thick = np.broadcast_to(x >= xs, b.shape)
+    p = rad_params(100.0, c=1000.0, kappa_P=0.0, kappa_R=1.0, cfl=0.3)
+    gamma = p["gamma"]
+    rho = np.where(thick, tau_thick, tau_thin) / (p["kappa_R"] * dx)
+    E = np.where(thick, e_thick, 1.0)
+    F = np.where(thick, 0.0, f_beam * p["c"] * E)
+    Ug = _alloc(b, 5)
+    Ur = _alloc(b, 4)
+    Ug[0] = rho
+    Ug[4] = rho * np.where(thick, tau_thin / tau_thick, 1.0) / (gamma - 1.0)
+    Ur[0] = E
+    Ur[1] = F * np.cos(ang)
+    Ur[2] = F * np.sin(ang)
+    return b, Ug, Ur, p
 
 
 def to_f32_and_back(U):
