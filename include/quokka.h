@@ -50,8 +50,13 @@ typedef enum {
 typedef enum { QK_F64 = 0, QK_MIXED = 1 } qk_precision;
 
 /* Boundary kind per box face.  PERIODIC must pair (lo and hi of one axis).
- * FIXED: the ghost cells are caller data and are never written. */
-typedef enum { QK_BC_PERIODIC = 0, QK_BC_OUTFLOW = 1, QK_BC_FIXED = 2 } qk_bc;
+ * FIXED: the ghost cells are caller data and are never written.
+ * FIXED_FREE_FLUX: Dirichlet ends that hold the gas state and the radiation
+ * energy but not the radiation flux (Section 3.3.1's radiation pressure tube:
+ * its steady state fixes rho, v and T): every variable is FIXED except
+ * F_x, F_y, F_z of a 4-variable (radiation) state, which are filled as
+ * OUTFLOW.  Not accepted by quokka_batch_step. */
+typedef enum { QK_BC_PERIODIC = 0, QK_BC_OUTFLOW = 1, QK_BC_FIXED = 2, QK_BC_FIXED_FREE_FLUX = 3 } qk_bc;
 
 typedef struct {
   int32_t n[3];        /* interior cells per axis, each >= 1                    */
@@ -90,7 +95,14 @@ typedef struct {
   int32_t nsub_max;       /* substep cap per hydro step (10 in the paper)      */
   int32_t closure;        /* 0 Levermore (M1), 1 Eddington (P = E/3 I),
                              2 Minerbo (polynomial form)                       */
-  int32_t tau_correction; /* 1: scale HLL dissipation by min(1, 1/tau_face)    */
+  int32_t tau_correction; /* 0 off; 1: optical-depth correction (Section 2.2.2):
+                             the HLL dissipation of every face is scaled by
+                             min(1, 1/tau), tau = dx kappa_R (rho_L + rho_R)/2,
+                             and switched off again at the faces of each cell
+                             where the corrected stage gives |F| > c E_r (the
+                             stage is then formed again there; both cells of
+                             such a face take the uncorrected flux).  Needs
+                             n[0] n[1] n[2] < 2^31 per box.                    */
   int32_t eos;            /* 0: P = rho T, E_g = rho T/(gamma-1); 1: alpha T^4 */
   int32_t reconstruction; /* 0 PPM, 1 PLM, for E_r and f (Section 2.2.2) and, in
                              quokka_rhd_step, for the hydro step as well       */

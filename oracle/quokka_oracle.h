@@ -9,12 +9,13 @@
  * code, header, constant or helper with the GPU library.
  *
  * Pins: the tests check every function against closed forms, invariants, the
- * paper's printed results or exact solutions.  One part is only partly
- * pinned: the optical-depth factor of the radiation HLL flux, whose formula
- * the paper does not give (its value is a reading; the radiation pressure
- * tube of Section 3.3.1 runs with it active and holds the paper's 0.2 per
- * cent over the whole column; the causality rule that disables it is pinned
- * by its defining properties).
+ * paper's printed results or exact solutions.  One formula is parity
+ * unpinned: the optical-depth factor min(1, 1/tau) of the radiation HLL
+ * flux, which the paper names but does not write down (a reading).  The
+ * radiation pressure tube of Section 3.3.1 runs with it active and holds the
+ * paper's 0.2 per cent over the whole column, but gives the same error with
+ * the factor off, so it does not fix the formula.  The causality rule that
+ * switches the factor off is pinned by its defining properties.
  *
  * Array layout used by every entry point: one contiguous float64 array per
  * state, shape (nvar, nz+2ng, ny+2ng, nx+2ng), x fastest.  Gas state has

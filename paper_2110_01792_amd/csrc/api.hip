@@ -30,7 +30,8 @@ struct Scalars {
   int32_t nsub;
   uint32_t err;               // sticky ERR_* bits
   uint32_t newton_iter_max;
-  uint32_t pad[9];
+  uint32_t nthick;            // length of the thick-cell list of the radiation step
+  uint32_t pad[8];
 };
 
 struct Buf {
@@ -109,6 +110,8 @@ struct qk_ctx {
   std::string last_error;
   Scalars* sc = nullptr;
   Buf stage_g, stage_r, chi;
+  Buf vflags;  // causality flags of the two radiation stages (kept zero between uses)
+  Buf tlist;   // thick-cell list of the radiation step
   BatchCache batch;
   KernelTimer timer;
 };
@@ -125,12 +128,16 @@ qk_status hip_check(qk_ctx* ctx, hipError_t e, const char* what) {
   return fail(ctx, QK_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-qk_status ensure(qk_ctx* ctx, Buf& b, size_t bytes) {
+qk_status ensure(qk_ctx* ctx, Buf& b, size_t bytes, bool zeroed = false) {
   if (b.bytes >= bytes) return QK_OK;
-  if (b.p) (void)hipFree(b.p);
+  if (b.p) {
+    (void)hipDeviceSynchronize();  // queued work may still use the old buffer
+    (void)hipFree(b.p);
+  }
   b.p = nullptr;
   b.bytes = 0;
   if (hipMalloc(&b.p, bytes) != hipSuccess) return fail(ctx, QK_ENOMEM, "scratch allocation failed");
+  if (zeroed && hipMemset(b.p, 0, bytes) != hipSuccess) return fail(ctx, QK_EHIP, "scratch clear failed");
   b.bytes = bytes;
   return QK_OK;
 }
@@ -149,7 +156,7 @@ qk_status check_box(qk_ctx* ctx, const qk_box* b, HostBox& hb) {
     if (b->n[d] < 1) return fail(ctx, QK_EINVAL, "box extent < 1");
     if (!(b->dx[d] > 0.0) || !std::isfinite(b->dx[d])) return fail(ctx, QK_EINVAL, "cell width must be > 0");
     for (int s = 0; s < 2; ++s)
-      if (b->bc[d][s] < 0 || b->bc[d][s] > 2) return fail(ctx, QK_EINVAL, "unknown boundary kind");
+      if (b->bc[d][s] < 0 || b->bc[d][s] > 3) return fail(ctx, QK_EINVAL, "unknown boundary kind");
     if ((b->bc[d][0] == QK_BC_PERIODIC) != (b->bc[d][1] == QK_BC_PERIODIC))
       return fail(ctx, QK_EINVAL, "periodic boundaries must pair");
   }
@@ -193,7 +200,7 @@ qk_status check_box(qk_ctx* ctx, const qk_box* b, HostBox& hb) {
   for (int a = 0; a < 3; ++a)
     for (int s = 0; s < 2; ++s) {
       hb.bc[a][s] = b->bc[a][s];
-      if (b->bc[a][s] == QK_BC_FIXED) hb.any_fixed = true;
+      if (b->bc[a][s] == QK_BC_FIXED || b->bc[a][s] == QK_BC_FIXED_FREE_FLUX) hb.any_fixed = true;
     }
   return QK_OK;
 }
@@ -215,16 +222,19 @@ qk_status check_rad(qk_ctx* ctx, const qk_rad_params* rp) {
   if (!(rp->c > 0) || !(rp->chat > 0) || !(rp->a_r > 0) || !(rp->gamma > 1.0) || !(rp->cfl > 0) ||
       !(rp->newton_tol > 0) || rp->newton_max_iter < 1 || rp->nsub_max < 1 || rp->closure < 0 ||
       rp->closure > 2 || rp->eos < 0 || rp->eos > 1 || !(rp->kappa_P >= 0) || !(rp->kappa_R >= 0) ||
-      (rp->eos == 1 && !(rp->alpha_cv > 0)) || rp->reconstruction < 0 || rp->reconstruction > 1)
+      (rp->eos == 1 && !(rp->alpha_cv > 0)) || rp->reconstruction < 0 || rp->reconstruction > 1 ||
+      rp->tau_correction < 0 || rp->tau_correction > 1)
     return fail(ctx, QK_EINVAL, "invalid radiation parameters");
   return QK_OK;
 }
 
 GhostBC ghost_bc(const HostBox& hb) {
   GhostBC g;
+  g.any_ff = 0;
   for (int a = 0; a < 3; ++a) {
     g.lo[a] = hb.bc[a][0];
     g.hi[a] = hb.bc[a][1];
+    if (g.lo[a] == QK_BC_FIXED_FREE_FLUX || g.hi[a] == QK_BC_FIXED_FREE_FLUX) g.any_ff = 1;
   }
   return g;
 }
@@ -467,7 +477,7 @@ void quokka_ctx_destroy(qk_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   batch_cache_clear(ctx->batch);
-  for (Buf* b : {&ctx->stage_g, &ctx->stage_r, &ctx->chi})
+  for (Buf* b : {&ctx->stage_g, &ctx->stage_r, &ctx->chi, &ctx->vflags, &ctx->tlist})
     if (b->p) (void)hipFree(b->p);
   if (ctx->sc) (void)hipFree(ctx->sc);
   delete ctx;

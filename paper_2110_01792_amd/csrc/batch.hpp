@@ -27,6 +27,7 @@ struct BatchBox {
   double gamma;
   int zc_stage, zc_flat;
   int recon;  // hydro reconstruction of this box (0 PPM, 1 PLM)
+  uint8_t* vf[2];  // causality flags of radiation stages 1 and 2 (library scratch) or NULL
 };
 
 struct WorkItem {
@@ -102,6 +103,36 @@ __global__ __launch_bounds__(NT) void batch_stage_kernel(const BatchBox<S, R>* _
   if (bad) atomicOr(err, ERR_NEG);
 }
 
+// Arguments of one radiation stage of batched box bb (ghosts are fixed data:
+// the stage buffer reads its ghost cells from the box's own state).
+template <class S, class R, int STAGE>
+__device__ __forceinline__ RadStageArgs<S, R> batch_rad_args(const BatchBox<S, R>& bb, const RadParamsDev& p,
+                                                             const double* dt_ptr, const int32_t* nsub_ptr, int N,
+                                                             int sub, uint32_t* err, uint32_t* iter_max) {
+  RadStageArgs<S, R> a;
+  a.Uin = STAGE == 1 ? bb.Ur : bb.Ur1;
+  a.Ugh = STAGE == 1 ? nullptr : bb.Ur;
+  a.Un = bb.Ur;
+  a.Uout = STAGE == 1 ? bb.Ur1 : bb.Ur;
+  a.Ug = bb.U;
+  a.b = bb.b;
+  a.p = p;
+  a.dt_ptr = dt_ptr;
+  a.nsub_ptr = nsub_ptr;
+  a.dt_val = 0.0;
+  a.nsub_val = N;
+  a.sub = sub;
+  a.zc = bb.zc_stage;
+  a.gx = a.gy = 1;
+  a.err = err;
+  a.iter_max = iter_max;
+  a.reg = nullptr;
+  a.vfl = bb.vf[STAGE - 1];
+  a.vfl_clear = bb.vf[2 - STAGE];
+  a.per = 0;
+  return a;
+}
+
 template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE>
 __global__ __launch_bounds__(NT, sizeof(S) == 4 ? 3 : 2) void batch_rad_kernel(const BatchBox<S, R>* __restrict__ boxes,
                                                               const WorkItem* __restrict__ items, int nitems,
@@ -118,31 +149,47 @@ __global__ __launch_bounds__(NT, sizeof(S) == 4 ? 3 : 2) void batch_rad_kernel(c
     const int it = next_item(counter, &slot);
     if (it >= nitems) break;
     const WorkItem w = items[it];
-    const BatchBox<S, R>& bb = boxes[w.box];
-    RadStageArgs<S, R> a;
-    a.Uin = STAGE == 1 ? bb.Ur : bb.Ur1;
-    a.Ugh = STAGE == 1 ? nullptr : bb.Ur;
-    a.Un = bb.Ur;
-    a.Uout = STAGE == 1 ? bb.Ur1 : bb.Ur;
-    a.Ug = bb.U;
-    a.b = bb.b;
-    a.p = p;
-    a.dt_ptr = dt_ptr;
-    a.nsub_ptr = nsub_ptr;
-    a.dt_val = 0.0;
-    a.nsub_val = N;
-    a.sub = sub;
-    a.zc = bb.zc_stage;
-    a.gx = a.gy = 1;
-    a.err = err;
-    a.iter_max = iter_max;
-    a.reg = nullptr;
+    const RadStageArgs<S, R> a =
+        batch_rad_args<S, R, STAGE>(boxes[w.box], p, dt_ptr, nsub_ptr, N, sub, err, iter_max);
     itmax = max(itmax, rad_tile<S, R, TX, TY, NT, SPLIT, STAGE>(a, w.bx, w.by, w.bz, N, sm, bad, nfail));
     __syncthreads();
   }
   if (bad) atomicOr(err, ERR_NEG);
   if (nfail) atomicOr(err, ERR_NEWTON);
   if (STAGE == 2) block_umax_to<NT>(itmax, iter_max);
+}
+
+// Thick cells (a face with tau > 1) of every radiation box: block row y
+// serves box y.
+template <class S, class R>
+__global__ __launch_bounds__(256) void batch_thick_list_kernel(const BatchBox<S, R>* __restrict__ boxes,
+                                                               double kappa, CellRef* list, uint32_t* count) {
+  const BatchBox<S, R>& bb = boxes[blockIdx.y];
+  if (!bb.Ur) return;
+  thick_list_box<S, R>(bb.b, bb.U, kappa, (int)blockIdx.y, (int64_t)blockIdx.x * 256 + threadIdx.x,
+                       (int64_t)gridDim.x * 256, list, count);
+}
+
+// Fix-up pass of one radiation stage over the thick cells of every box.
+template <class S, class R, int STAGE>
+__global__ __launch_bounds__(256) void batch_rad_fix_kernel(const BatchBox<S, R>* __restrict__ boxes, RadParamsDev p,
+                                                            const double* dt_ptr, const int32_t* nsub_ptr, int sub,
+                                                            const CellRef* __restrict__ list, const uint32_t* count,
+                                                            uint32_t* err, uint32_t* iter_max) {
+  const int N = *nsub_ptr;
+  if (sub >= N) return;
+  const uint32_t n = *count;
+  bool bad = false, nfail = false;
+  uint32_t itmax = 0;
+  for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n; t += gridDim.x * 256u) {
+    const CellRef c = list[t];
+    const RadStageArgs<S, R> a = batch_rad_args<S, R, STAGE>(boxes[c.box], p, dt_ptr, nsub_ptr, N, sub, err, iter_max);
+    itmax = max(itmax, rad_fix_cell<S, R, STAGE>(a, c.i, c.j, c.k, N, bad, nfail));
+    a.vfl_clear[interior_index(a.b, c.i, c.j, c.k)] = 0;
+  }
+  if (bad) atomicOr(err, ERR_NEG);
+  if (nfail) atomicOr(err, ERR_NEWTON);
+  if (STAGE == 2) block_umax_to<256>(itmax, iter_max);
 }
 
 // Level CFL: max over every interior cell of every box of |v| + c_s (each box

@@ -847,12 +847,15 @@ __global__ void finalize_dt_kernel(unsigned long long* smax_bits, double cfl, do
 // ---------------------------------------------------------------------------
 // Ghost fill with the result of an x, then y (over the full x extent), then z
 // (over the full x-y extent) sequential fill: periodic wrap, zero-gradient
-// outflow, fixed faces untouched.  Sources are never written by the same
-// launch (their first out-of-range axis in z, y, x order is a fixed face), so
-// one launch fills all ghosts without ordering.
+// outflow, fixed faces untouched.  A fixed face with a free radiation flux
+// (kind 3) is fixed for every variable except F_x, F_y, F_z of a 4-variable
+// (radiation) state, which it fills as outflow.  Sources are never written by
+// the same launch (their first out-of-range axis in z, y, x order is a fixed
+// face), so one launch fills all ghosts without ordering.
 // ---------------------------------------------------------------------------
 struct GhostBC {
   int lo[3], hi[3];
+  int any_ff;  // some face is of kind 3
 };
 
 __device__ __forceinline__ int map_index(int i, int n, int lo, int hi) {
@@ -894,34 +897,47 @@ __device__ __forceinline__ void ghost_cell(const DevBox& b, int64_t c, int& i, i
   }
 }
 
+// Source cell of ghost (i, j, k), or false if the fill leaves it as it is.
+// The x, y, z sequential fill writes a ghost cell in the fill of the last axis
+// (in x, y, z order) along which it lies outside; a fixed face there leaves
+// it as it is.  Its value comes from the cell mapped along that axis, which in
+// turn was filled by the previous axes: map z, then y, then x, stopping at the
+// first fixed face met.  free_flux: kind 3 acts as outflow (else as fixed).
+__device__ __forceinline__ bool ghost_src(const DevBox& b, const GhostBC& bc, bool free_flux, int i, int j, int k,
+                                          int64_t& src) {
+  auto kind = [&](int kd) { return kd == 3 ? (free_flux ? 1 : 2) : kd; };
+  int si = i, sj = j, sk = k;
+  bool stop = false;
+  if (k < 0 || k >= b.n2) {
+    const int lo = kind(bc.lo[2]), hi = kind(bc.hi[2]);
+    if ((k < 0 ? lo : hi) == 2) stop = true; else sk = map_index(k, b.n2, lo, hi);
+  }
+  if (!stop && (j < 0 || j >= b.n1)) {
+    const int lo = kind(bc.lo[1]), hi = kind(bc.hi[1]);
+    if ((j < 0 ? lo : hi) == 2) stop = true; else sj = map_index(j, b.n1, lo, hi);
+  }
+  if (!stop && (i < 0 || i >= b.n0)) {
+    const int lo = kind(bc.lo[0]), hi = kind(bc.hi[0]);
+    if ((i < 0 ? lo : hi) != 2) si = map_index(i, b.n0, lo, hi);
+  }
+  if (si == i && sj == j && sk == k) return false;
+  src = cell(b, si, sj, sk);
+  return true;
+}
+
 template <class S>
 __device__ __forceinline__ void ghost_body(S* __restrict__ U, const DevBox& b, const GhostBC& bc, int nvar) {
   const int64_t total = ghost_count(b);
+  const bool ff = bc.any_ff && nvar == 4;  // radiation flux filled on its own
   for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < total; c += (int64_t)gridDim.x * 256) {
     int i, j, k;
     ghost_cell(b, c, i, j, k);
-    // The x, y, z sequential fill writes a ghost cell in the fill of the last
-    // axis (in x, y, z order) along which it lies outside; a fixed face there
-    // leaves it as it is.  Its value comes from the cell mapped along that
-    // axis, which in turn was filled by the previous axes: map z, then y,
-    // then x, stopping at the first fixed face met.
-    int si = i, sj = j, sk = k;
-    bool stop = false;
-    if (k < 0 || k >= b.n2) {
-      const int kind = k < 0 ? bc.lo[2] : bc.hi[2];
-      if (kind == 2) stop = true; else sk = map_index(k, b.n2, bc.lo[2], bc.hi[2]);
-    }
-    if (!stop && (j < 0 || j >= b.n1)) {
-      const int kind = j < 0 ? bc.lo[1] : bc.hi[1];
-      if (kind == 2) stop = true; else sj = map_index(j, b.n1, bc.lo[1], bc.hi[1]);
-    }
-    if (!stop && (i < 0 || i >= b.n0)) {
-      const int kind = i < 0 ? bc.lo[0] : bc.hi[0];
-      if (kind != 2) si = map_index(i, b.n0, bc.lo[0], bc.hi[0]);
-    }
-    if (si == i && sj == j && sk == k) continue;
-    const int64_t dst = cell(b, i, j, k), src = cell(b, si, sj, sk);
-    for (int v = 0; v < nvar; ++v) U[dst + v * b.vs] = U[src + v * b.vs];
+    const int64_t dst = cell(b, i, j, k);
+    int64_t src;
+    if (ghost_src(b, bc, false, i, j, k, src))
+      for (int v = 0; v < (ff ? 1 : nvar); ++v) U[dst + v * b.vs] = U[src + v * b.vs];
+    if (ff && ghost_src(b, bc, true, i, j, k, src))
+      for (int v = 1; v < 4; ++v) U[dst + v * b.vs] = U[src + v * b.vs];
   }
 }
 

@@ -41,7 +41,30 @@ struct RadStageArgs {
   double* reg;             // rad_region_flux_kernel: flux register over the faces
   int rlo[3], rhi[3];      //   bounding [rlo, rhi) (the stage kernel ignores these)
   double rw;               //   register weight: each face adds rw * dt_sub/2 * F
+  // Causality rule of the optical-depth correction (used when tau_correction
+  // is on): one byte per interior cell, index i + n0 (j + n1 k).
+  uint8_t* vfl;            // set to 1 by this stage at cells that violate |F| <= c E_r
+  uint8_t* vfl_clear;      // flags of the other stage, cleared by this stage's fix-up
+  int per;                 // bit d set: axis d is periodic (a face there joins both ends)
 };
+
+// A cell of a thick-cell list: box index (0 for a single box) and cell.
+struct CellRef {
+  int box, i, j, k;
+};
+
+__device__ __forceinline__ int64_t interior_index(const DevBox& b, int i, int j, int k) {
+  return (int64_t)i + (int64_t)b.n0 * ((int64_t)j + (int64_t)b.n1 * k);
+}
+
+// Optical depth of a face (Section 2.2.2; the formula is a reading: tau = dx
+// kappa_R (rho_L + rho_R)/2) exceeds 1, so the correction scales its flux.
+// The stage kernel, the fix-up and the thick-cell list all decide with this
+// one expression.
+template <class R>
+__device__ __forceinline__ R face_tau(R dxd, R kappa, R rhol, R rhor) {
+  return dxd * kappa * (R(0.5) * (rhol + rhor));
+}
 
 // HLL flux of (E, F) along axis d between face states (E, f), f.f = ffL, ffR
 // (Section 2.2.2).  The wave speed chat max(sqrt(T_dd^L), sqrt(T_dd^R)) is
@@ -70,11 +93,13 @@ __device__ __forceinline__ void rad_flux(R EL, R fLx, R fLy, R fLz, R ffL, R ER,
 
 // Face between cell "l" (reconstructed right state aL*) and cell "r": choose
 // the reconstructed states or, if either |f| exceeds 1, both cell averages,
-// then the optical-depth factor, then the flux.  cells(cl, cr) fetches the
+// then the optical-depth factor (on every optically thick face, fallback
+// faces included), then the flux.  cells(cl, cr) fetches the
 // two cell averages; the fallback is rare, so whole waves skip the fetch.
 template <class R, class Cells>
 __device__ __forceinline__ void rad_face(const R* sl, const R* sr, const Cells& cells, R rhol, R rhor, R dxd,
-                                         int d, const RadParamsDev& p, R c, R chat, R ratio, R cc, R* out) {
+                                         int d, const RadParamsDev& p, R c, R chat, R ratio, R cc, R* out,
+                                         bool tau_off = false) {
   R ffl = (sl[1] * sl[1] + sl[2] * sl[2]) + sl[3] * sl[3];  // f.f of each side
   R ffr = (sr[1] * sr[1] + sr[2] * sr[2]) + sr[3] * sr[3];
   const bool fb = f_above_one(ffl) || f_above_one(ffr);
@@ -92,9 +117,10 @@ __device__ __forceinline__ void rad_face(const R* sl, const R* sr, const Cells& 
   R eps = R(1);
   if (p.tau_correction) {
     // min(1, 1/tau) is 1 unless tau > 1: waves with no optically thick face
-    // skip the division (a wave-uniform branch)
-    const R tau = dxd * R(p.kappa_R) * (R(0.5) * (rhol + rhor));
-    const bool thick = !fb && tau > R(1);
+    // skip the division (a wave-uniform branch).  tau_off: the face touches a
+    // cell where the causality rule switched the correction off.
+    const R tau = face_tau<R>(dxd, R(p.kappa_R), rhol, rhor);
+    const bool thick = !tau_off && tau > R(1);
     if (__ballot(thick)) eps = thick ? R(1) / tau : R(1);
   }
   rad_flux<R>(L[0], L[1], L[2], L[3], ffl, Rr[0], Rr[1], Rr[2], Rr[3], ffr, d, p.closure, c, chat, ratio, cc, eps, out);
@@ -279,7 +305,7 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
 
   R w[4][5];  // own column (E, fx, fy, fz): [var][slot], slot s = plane m-2+s
   R aRz[4], Fz[4];
-  R rz_k = R(0), rz_k1 = R(0);  // density of own column at k and k+1 (tau correction)
+  R rz_km1 = R(0), rz_k = R(0), rz_k1 = R(0);  // density of own column at k-1, k, k+1 (tau correction)
   double cq[4];                 // own column, plane k+3 (prefetched)
   double hq[HPT][4];            // halo ring of plane k (prefetched)
   double uo[4], un0[4], gas[5];
@@ -364,6 +390,7 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
         rl, rr, R(b.dx2), 2, p, c, chat, ratio, cc, Fz);
 #pragma unroll
     for (int v = 0; v < 4; ++v) aRz[v] = rcur[v];
+    rz_k = rl;
     rz_k1 = rr;
     load4(src_at(Uin, a.Ugh, b, i, j, z0 + 3), cell(b, i, j, z0 + 3), cq);
   }
@@ -383,6 +410,7 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
         Qp[v][ty + 3][tx + 3] = w[v][1];
       }
       if (tauc) {
+        rz_km1 = rz_k;
         rz_k = rz_k1;
         rhoP[ty + 1][tx + 1] = rz_k;
       }
@@ -417,6 +445,16 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
       for (int m = 0; m < HPT; ++m) load_halo<4>(hc[m], hc[m].src, Ug, (int64_t)(k + 1) * pz, vs, hq[m]);
     }
     __syncthreads();
+    // Does an x or y face of the own cell have tau > 1?  (Read here: the
+    // density plane is rewritten for the next plane before its first barrier.)
+    bool thick_xy = false;
+    if (tauc && act) {
+      const R kap = R(p.kappa_R), dx0 = R(b.dx0), dx1 = R(b.dx1);
+      thick_xy = face_tau<R>(dx0, kap, rhoP[ty + 1][tx], rz_k) > R(1) ||
+                 face_tau<R>(dx0, kap, rz_k, rhoP[ty + 1][tx + 2]) > R(1) ||
+                 face_tau<R>(dx1, kap, rhoP[ty][tx + 1], rz_k) > R(1) ||
+                 face_tau<R>(dx1, kap, rz_k, rhoP[ty + 2][tx + 1]) > R(1);
+    }
 
     auto x_recon = [&]() {
       for (int it = t; it < NXR; it += NT) {
@@ -560,15 +598,30 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
         Fz[v] = Fk[v];
         aRz[v] = aRn[v];
       }
-      if (STAGE == 2) {
-        const int it = exchange(p, dt, dt * srate, gas, un, nfail);
-        itmax = max(itmax, (uint32_t)it);
-#pragma unroll
-        for (int v = 1; v < 5; ++v) a.Ug[o + v * vs] = S(gas[v]);
+      // Causality rule (Section 2.2.2): a cell with an optically thick face
+      // (a "thick cell") whose corrected update gives |F| > c E_r is flagged;
+      // the fix-up pass redoes the thick cells next to flagged ones with the
+      // correction off at the flagged cells' faces.  Stage 2 leaves thick
+      // cells (update and coupling) entirely to that pass, and stage 1 leaves
+      // it their positivity check.
+      bool thick = false;
+      if (tauc) {
+        const R kap = R(p.kappa_R), dx2 = R(b.dx2);
+        thick = thick_xy || face_tau<R>(dx2, kap, rz_km1, rz_k) > R(1) || face_tau<R>(dx2, kap, rz_k, rz_k1) > R(1);
+        if (thick && sqrt((un[1] * un[1] + un[2] * un[2]) + un[3] * un[3]) > p.c * un[0])
+          a.vfl[interior_index(b, i, j, k)] = 1;
       }
+      if (STAGE == 1 || !thick) {
+        if (STAGE == 2) {
+          const int it = exchange(p, dt, dt * srate, gas, un, nfail);
+          itmax = max(itmax, (uint32_t)it);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) a.Uout[o + v * vs] = S(un[v]);
-      bad = bad || !(un[0] > 0.0);
+          for (int v = 1; v < 5; ++v) a.Ug[o + v * vs] = S(gas[v]);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) a.Uout[o + v * vs] = S(un[v]);
+        if (!thick) bad = bad || !(un[0] > 0.0);
+      }
     }
   }
   bad_out = bad_out || bad;
@@ -590,67 +643,239 @@ __global__ __launch_bounds__(SNT, sizeof(S) == 4 ? 3 : 2) void rad_stage_kernel(
 }
 
 
+// Flux of the radiation stage input through the face between cells
+// (i, j, k) - e_d and (i, j, k), computed with the stage kernel's own device
+// functions on the same operands (the same bits as the stage kernel's face).
+// tau_off: the optical-depth correction is off at this face.
+template <class S, class R>
+__device__ __forceinline__ void rad_flux_at(const RadStageArgs<S, R>& a, int d, int i, int j, int k, bool tau_off,
+                                            R* F) {
+  const DevBox& b = a.b;
+  const RadParamsDev& p = a.p;
+  const R c = R(p.c), chat = R(p.chat), ratio = R(p.chat / p.c), cc = R(p.c * p.chat);
+  const int ei = d == 0, ej = d == 1, ek = d == 2;
+  R Q[6][4];  // (E, f = F / (c E)) of cells f-3 .. f+2 along d
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int ii = i + ei * (s - 3), jj = j + ej * (s - 3), kk = k + ek * (s - 3);
+    const S* src = src_at(a.Uin, a.Ugh, b, ii, jj, kk);
+    const int64_t o = cell(b, ii, jj, kk);
+    const R Er = R(double(src[o]));
+    const R inv = R(1) / (c * Er);
+    Q[s][0] = Er;
+#pragma unroll
+    for (int v = 1; v < 4; ++v) Q[s][v] = R(double(src[o + v * b.vs])) * inv;
+  }
+  R sl[4], sr[4], tmp[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    recon5<R>(Q[0][v], Q[1][v], Q[2][v], Q[3][v], Q[4][v], p.recon, tmp[v], sl[v]);  // cell f-1, right
+    recon5<R>(Q[1][v], Q[2][v], Q[3][v], Q[4][v], Q[5][v], p.recon, sr[v], tmp[v]);  // cell f, left
+  }
+  R rl = R(0), rr = R(0);
+  if (p.tau_correction) {
+    rl = R(a.Ug[cell(b, i - ei, j - ej, k - ek)]);
+    rr = R(a.Ug[cell(b, i, j, k)]);
+  }
+  rad_face<R>(
+      sl, sr,
+      [&](R* cl, R* cr) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          cl[v] = Q[2][v];
+          cr[v] = Q[3][v];
+        }
+      },
+      rl, rr, R(d == 0 ? b.dx0 : (d == 1 ? b.dx1 : b.dx2)), d, p, c, chat, ratio, cc, F, tau_off);
+}
+
+// Causality flag of cell (i, j, k) set by the stage: across a periodic axis a
+// cell outside the box is its image; any other cell outside never violates.
+template <class S, class R>
+__device__ __forceinline__ bool vflag_at(const RadStageArgs<S, R>& a, int i, int j, int k) {
+  const DevBox& b = a.b;
+  if ((unsigned)i >= (unsigned)b.n0) {
+    if (!(a.per & 1)) return false;
+    i = ((i % b.n0) + b.n0) % b.n0;
+  }
+  if ((unsigned)j >= (unsigned)b.n1) {
+    if (!(a.per & 2)) return false;
+    j = ((j % b.n1) + b.n1) % b.n1;
+  }
+  if ((unsigned)k >= (unsigned)b.n2) {
+    if (!(a.per & 4)) return false;
+    k = ((k % b.n2) + b.n2) % b.n2;
+  }
+  return a.vfl[interior_index(b, i, j, k)] != 0;
+}
+
+// Is any face of cell (i, j, k) optically thick (tau > 1)?  The density of
+// the gas state, ghosts included, decides; it does not change during a
+// radiation step, so neither does the answer.
+template <class S, class R>
+__device__ __forceinline__ bool cell_is_thick(const DevBox& b, const S* Ug, R kap, int i, int j, int k) {
+  const R rc = R(Ug[cell(b, i, j, k)]);
+  bool th = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int ei = d == 0, ej = d == 1, ek = d == 2;
+    const R dxd = R(d == 0 ? b.dx0 : (d == 1 ? b.dx1 : b.dx2));
+    const R rlo = R(Ug[cell(b, i - ei, j - ej, k - ek)]), rhi = R(Ug[cell(b, i + ei, j + ej, k + ek)]);
+    th = th || face_tau<R>(dxd, kap, rlo, rc) > R(1) || face_tau<R>(dxd, kap, rc, rhi) > R(1);
+  }
+  return th;
+}
+
+// Fix-up of one thick cell after a radiation stage (the causality rule of
+// Section 2.2.2).  A face is uncorrected when either of its cells was flagged
+// by the stage; the cell's update is formed again from the stage input with
+// those faces (a face is one flux for both of its cells, so the update stays
+// conservative).  STAGE 1: only where a thick face of the cell switched; the
+// positivity check of the final value either way.  STAGE 2: always (the
+// stage kernel left the cell), followed by the coupling of Section 2.2.3.
+// Returns the exchange iterations used.
+template <class S, class R, int STAGE>
+__device__ __forceinline__ uint32_t rad_fix_cell(const RadStageArgs<S, R>& a, int i, int j, int k, int N, bool& bad,
+                                                 bool& nfail) {
+  const DevBox& b = a.b;
+  const RadParamsDev& p = a.p;
+  const int64_t vs = b.vs, o = cell(b, i, j, k);
+  const R kap = R(p.kappa_R), rc = R(a.Ug[o]);
+  const bool vc = vflag_at(a, i, j, k);
+  bool sw[3][2];
+  bool any = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int ei = d == 0, ej = d == 1, ek = d == 2;
+    const R dxd = R(d == 0 ? b.dx0 : (d == 1 ? b.dx1 : b.dx2));
+    const R rlo = R(a.Ug[cell(b, i - ei, j - ej, k - ek)]), rhi = R(a.Ug[cell(b, i + ei, j + ej, k + ek)]);
+    sw[d][0] = vc || vflag_at(a, i - ei, j - ej, k - ek);
+    sw[d][1] = vc || vflag_at(a, i + ei, j + ej, k + ek);
+    any = any || (sw[d][0] && face_tau<R>(dxd, kap, rlo, rc) > R(1)) ||
+          (sw[d][1] && face_tau<R>(dxd, kap, rc, rhi) > R(1));
+  }
+  if (STAGE == 1 && !any) {
+    bad = bad || !(double(a.Uout[o]) > 0.0);
+    return 0;
+  }
+  R Flo[3][4], Fhi[3][4];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    rad_flux_at<S, R>(a, d, i, j, k, sw[d][0], Flo[d]);
+    rad_flux_at<S, R>(a, d, i + (d == 0), j + (d == 1), k + (d == 2), sw[d][1], Fhi[d]);
+  }
+  const double dt = (a.dt_ptr ? *a.dt_ptr : a.dt_val) / N;
+  double un[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const double uo = double(a.Uin[o + v * vs]);
+    const double tX = double(Fhi[0][v] - Flo[0][v]) * b.inv_dx0;
+    const double tY = double(Fhi[1][v] - Flo[1][v]) * b.inv_dx1;
+    const double tZ = double(Fhi[2][v] - Flo[2][v]) * b.inv_dx2;
+    const double L = -((tX + tY) + tZ);
+    un[v] = (STAGE == 1) ? uo + dt * L : 0.5 * double(a.Un[o + v * vs]) + 0.5 * (uo + dt * L);
+  }
+  uint32_t it = 0;
+  if (STAGE == 2) {
+    double gas[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) gas[v] = double(a.Ug[o + v * vs]);
+    const double srate = p.src ? double(((const S*)p.src)[o]) : 0.0;
+    it = (uint32_t)exchange(p, dt, dt * srate, gas, un, nfail);
+#pragma unroll
+    for (int v = 1; v < 5; ++v) a.Ug[o + v * vs] = S(gas[v]);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) a.Uout[o + v * vs] = S(un[v]);
+  bad = bad || !(un[0] > 0.0);
+  return it;
+}
+
+// Append every thick cell of one box to `list` (wave-aggregated atomics).
+template <class S, class R>
+__device__ __forceinline__ void thick_list_box(const DevBox& b, const S* Ug, double kappa, int box, int64_t t0,
+                                               int64_t stride, CellRef* list, uint32_t* count) {
+  const int64_t n = (int64_t)b.n0 * b.n1 * b.n2;
+  const int lane = threadIdx.x & 63;
+  for (int64_t base = t0 - lane; base < n; base += stride) {  // whole waves iterate together
+    const int64_t t = base + lane;
+    bool th = false;
+    int i = 0, j = 0, k = 0;
+    if (t < n) {
+      i = (int)(t % b.n0);
+      j = (int)((t / b.n0) % b.n1);
+      k = (int)(t / ((int64_t)b.n0 * b.n1));
+      th = cell_is_thick<S, R>(b, Ug, R(kappa), i, j, k);
+    }
+    const unsigned long long m = __ballot(th);
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      uint32_t q = 0;
+      if (lane == leader) q = atomicAdd(count, (uint32_t)__popcll(m));
+      q = (uint32_t)__shfl((int)q, leader, 64);
+      if (th) list[q + __popcll(m & ((1ull << lane) - 1ull))] = CellRef{box, i, j, k};
+    }
+  }
+}
+
+template <class S, class R>
+__global__ __launch_bounds__(256) void thick_list_kernel(const S* Ug, DevBox b, double kappa, CellRef* list,
+                                                         uint32_t* count) {
+  thick_list_box<S, R>(b, Ug, kappa, 0, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256, list,
+                       count);
+}
+
+__global__ void zero_u32_kernel(uint32_t* x) { *x = 0u; }
+
+// Fix-up pass of one radiation stage over the thick cells of a box; also
+// clears the other stage's flags at those cells.  Guarded by the device
+// substep count like the stage.
+template <class S, class R, int STAGE>
+__global__ __launch_bounds__(256) void rad_fix_kernel(RadStageArgs<S, R> a, const CellRef* __restrict__ list,
+                                                      const uint32_t* count) {
+  const int N = a.nsub_ptr ? *a.nsub_ptr : a.nsub_val;
+  if (a.sub >= N) return;
+  const uint32_t n = *count;
+  bool bad = false, nfail = false;
+  uint32_t itmax = 0;
+  for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n; t += gridDim.x * 256u) {
+    const CellRef c = list[t];
+    itmax = max(itmax, rad_fix_cell<S, R, STAGE>(a, c.i, c.j, c.k, N, bad, nfail));
+    a.vfl_clear[interior_index(a.b, c.i, c.j, c.k)] = 0;
+  }
+  if (bad) atomicOr(a.err, ERR_NEG);
+  if (nfail) atomicOr(a.err, ERR_NEWTON);
+  if (STAGE == 2) block_umax_to<256>(itmax, a.iter_max);
+}
+
 // Flux register of one radiation stage: the fluxes at the faces bounding
 // region [rlo, rhi), recomputed from the stage input (and the gas density
 // for the optical-depth factor) with the stage kernel's own device functions
-// on the same operands, so every face carries the bits the stage used; each
-// adds rw * dt_sub/2 * F to its slot.  One thread per face; guarded by the
-// device substep count like the stage.  Launched after the stage, which
-// leaves its input and the density as they were.
+// on the same operands, so every face carries the bits the stage used (with
+// the causality rule's choice, from the stage's flags); each adds
+// rw * dt_sub/2 * F to its slot.  One thread per face; guarded by the device
+// substep count like the stage.  Launched after the stage, which leaves its
+// input and the density as they were.
 template <class S, class R>
 __global__ __launch_bounds__(256) void rad_region_flux_kernel(RadStageArgs<S, R> a) {
   const int N = a.nsub_ptr ? *a.nsub_ptr : a.nsub_val;
   if (a.sub >= N) return;
-  const DevBox& b = a.b;
-  const RadParamsDev& p = a.p;
   const int lo[3] = {a.rlo[0], a.rlo[1], a.rlo[2]}, hi[3] = {a.rhi[0], a.rhi[1], a.rhi[2]};
   const int64_t total = region_face_count(lo, hi);
   const double dt = (a.dt_ptr ? *a.dt_ptr : a.dt_val) / N;
   const double w = 0.5 * dt * a.rw;
-  const R c = R(p.c), chat = R(p.chat), ratio = R(p.chat / p.c), cc = R(p.c * p.chat);
-  const bool tauc = p.tau_correction != 0;
+  const bool rule = a.p.tau_correction != 0 && a.vfl;
   for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
     const RegionFace rf = region_face(lo, hi, t);
     const int d = rf.d;
-    // cell f along d (the face lies between cells f-1 and f); unit step e along d
+    // cell f along d (the face lies between cells f-1 and f)
     const int ei = d == 0, ej = d == 1, ek = d == 2;
     const int i = d == 0 ? (rf.side ? hi[0] : lo[0]) : lo[0] + rf.b;
     const int j = d == 1 ? (rf.side ? hi[1] : lo[1]) : (d == 0 ? lo[1] + rf.b : lo[1] + rf.a);
     const int k = d == 2 ? (rf.side ? hi[2] : lo[2]) : lo[2] + rf.a;
-    R Q[6][4];  // (E, f = F / (c E)) of cells f-3 .. f+2 along d
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-      const int ii = i + ei * (s - 3), jj = j + ej * (s - 3), kk = k + ek * (s - 3);
-      const S* src = src_at(a.Uin, a.Ugh, b, ii, jj, kk);
-      const int64_t o = cell(b, ii, jj, kk);
-      const R Er = R(double(src[o]));
-      const R inv = R(1) / (c * Er);
-      Q[s][0] = Er;
-#pragma unroll
-      for (int v = 1; v < 4; ++v) Q[s][v] = R(double(src[o + v * b.vs])) * inv;
-    }
-    R sl[4], sr[4], tmp[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      recon5<R>(Q[0][v], Q[1][v], Q[2][v], Q[3][v], Q[4][v], p.recon, tmp[v], sl[v]);  // cell f-1, right
-      recon5<R>(Q[1][v], Q[2][v], Q[3][v], Q[4][v], Q[5][v], p.recon, sr[v], tmp[v]);  // cell f, left
-    }
-    R rl = R(0), rr = R(0);
-    if (tauc) {
-      rl = R(a.Ug[cell(b, i - ei, j - ej, k - ek)]);
-      rr = R(a.Ug[cell(b, i, j, k)]);
-    }
+    const bool off = rule && (vflag_at(a, i - ei, j - ej, k - ek) || vflag_at(a, i, j, k));
     R F[4];
-    rad_face<R>(
-        sl, sr,
-        [&](R* cl, R* cr) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            cl[v] = Q[2][v];
-            cr[v] = Q[3][v];
-          }
-        },
-        rl, rr, R(d == 0 ? b.dx0 : (d == 1 ? b.dx1 : b.dx2)), d, p, c, chat, ratio, cc, F);
+    rad_flux_at<S, R>(a, d, i, j, k, off, F);
 #pragma unroll
     for (int v = 0; v < 4; ++v) a.reg[reg_slot(lo, hi, d, v, rf.side, rf.a, rf.b, 4)] += w * double(F[v]);
   }

@@ -299,3 +299,137 @@ def test_rhd_padded_layout_equals_contiguous_bitwise(ctx):
     assert np.array_equal(host(R), host(PR.contiguous()))
     with pytest.raises(ValueError):
         ctx.rhd_step(b, G, PR, rp)
+
+
+# ------------------------------------- causality rule of the optical-depth correction
+def _oracle_rhd_counting(b, Ug, Ur, p, nsteps):
+    G, R = Ug.copy(), Ur.copy()
+    causal = 0
+    for _ in range(nsteps):
+        st = oracle.rhd_step(b, G, R, p)
+        assert st["neg_cells"] == 0 and st["newton_fail"] == 0
+        causal += st["causal_cells"]
+    return G, R, causal
+
+
+@pytest.mark.parametrize("n,nsteps", [((32, 1, 1), 3), ((24, 12, 8), 2), ((40, 20, 12), 1)])
+def test_causality_rule_matches_oracle(ctx, n, nsteps):
+    """Section 2.2.2: a beam (|f| = 0.99) enters an optically thick slab
+    (tau_cell 100 beside 0.01, curved surface in 3-D), so thick faces sit
+    beside streaming ones and the corrected update gives |F| > c E_r at the
+    slab's surface.  The oracle switches the correction off there (its count
+    of such cells is > 0); the GPU matches it after whole RHD steps, in 1-D,
+    in 3-D and on a box spanning several tiles with partial ones."""
+    b, Ug, Ur, p = inputs.rad_thick_streaming(n=n)
+    gg, gr, st = gpu_rhd(ctx, b, Ug, Ur, p, nsteps)
+    assert st == qb.QK_OK
+    og, orr, causal = _oracle_rhd_counting(b, Ug, Ur, p, nsteps)
+    assert causal > 0
+    check_pair((gg, gr), (og, orr), b, f"causality rule n={n}")
+    # without the correction the result differs (the rule's cells matter)
+    ng, nr, _ = oracle_rhd(b, Ug, Ur, dict(p, tau_correction=0), nsteps)
+    assert np.max(np.abs(nr[0] - orr[0])) > 1e-6 * np.max(np.abs(orr[0]))
+
+
+def test_causality_rule_mixed_precision_stays_causal_and_positive(ctx):
+    """The FP32 path on the thick slab: the rule keeps it positive and close
+    to the FP64 oracle (L1 per variable, C.8's metric, bar 1e-5 is for smooth
+    workloads; here 1e-3 on a discontinuous slab)."""
+    torch = pytest.importorskip("torch")
+    b, Ug, Ur, p = inputs.rad_thick_streaming(n=(24, 12, 8))
+    G, R = dev(Ug, torch.float32), dev(Ur, torch.float32)
+    ctx.fill_ghosts(b, G)
+    ctx.fill_ghosts(b, R)
+    ctx.rhd_step(b, G, R, qb.rad_params(p))
+    assert ctx.sync_status() == qb.QK_OK
+    og, orr, causal = _oracle_rhd_counting(b, host(dev(Ug, torch.float32)), host(dev(Ur, torch.float32)), p, 1)
+    from tests.gpu_util import norm_l1
+    assert np.all(norm_l1(host(R), orr, b) < 1e-3), norm_l1(host(R), orr, b)
+    assert np.all(norm_l1(host(G), og, b) < 1e-3), norm_l1(host(G), og, b)
+
+
+def test_causality_rule_in_batched_level(ctx):
+    """The rule inside the batched level step: two slab boxes with fixed ghost
+    cells (filled beforehand) and one hydro-only box, three level steps (one
+    capture, two graph replays), against the oracle's level step."""
+    torch = pytest.importorskip("torch")
+    boxes, Gs, Rs = [], [], []
+    for n, seed in (((24, 12, 8), 9), ((16, 16, 8), 19)):
+        b, Ug, Ur, p = inputs.rad_thick_streaming(n=n, seed=seed)
+        oracle.fill_ghosts(b, Ug)
+        oracle.fill_ghosts(b, Ur)
+        boxes.append(b._replace(bc=((inputs.FIXED, inputs.FIXED),) * 3))
+        Gs.append(Ug)
+        Rs.append(Ur)
+    hb, hU, _ = inputs.hydro_smooth(n=16)
+    oracle.fill_ghosts(hb, hU)
+    boxes.append(hb._replace(bc=((inputs.FIXED, inputs.FIXED),) * 3))
+    Gs.append(hU)
+    Rs.append(None)
+    hp = {"gamma": p["gamma"], "cfl": p["cfl"]}
+    G = [dev(u) for u in Gs]
+    R = [None if u is None else dev(u) for u in Rs]
+    oG = [u.copy() for u in Gs]
+    oR = [None if u is None else u.copy() for u in Rs]
+    causal = 0
+    for s in range(3):
+        ctx.batch_step(boxes, G, R, qb.hydro_params(hp["gamma"], hp["cfl"]), qb.rad_params(p))
+        st = oracle.batch_step(boxes, oG, oR, hp["gamma"], hp["cfl"], p)
+        causal += st["causal_cells"]
+        for k, b in enumerate(boxes):
+            e = rel_linf(host(G[k]), oG[k], b)
+            assert np.all(e <= TOL), (s, k, "gas", e)
+            if oR[k] is not None:
+                e = rel_linf(host(R[k]), oR[k], b)
+                assert np.all(e <= TOL), (s, k, "rad", e, worst_cell(host(R[k]), oR[k], b))
+    assert ctx.sync_status() == qb.QK_OK
+    assert causal > 0
+
+
+def test_rad_pressure_tube_whole_column_within_paper_bound(ctx):
+    """Section 3.3.1: over one sound-crossing time (CFL 0.4, 128 cells,
+    tau_cell ~ 100) the GPU keeps gas and radiation temperatures within the
+    paper's 0.2 per cent of the ODE steady state over the whole column
+    (Dirichlet ends hold rho, v and T; the radiation flux in the ghost cells is
+    extrapolated), with T_rad = T_gas; and it stays within 1e-9 of the oracle
+    run with the same step sizes."""
+    torch = pytest.importorskip("torch")
+    b, Ug, Ur, p, ref = inputs.rad_pressure_tube()
+    G, R = dev(Ug), dev(Ur)
+    ctx.fill_ghosts(b, G)
+    ctx.fill_ghosts(b, R)
+    rp = qb.rad_params(p)
+    hp = qb.hydro_params(p["gamma"], p["cfl"], p["recon"])
+    oG, oR = Ug.copy(), Ur.copy()
+    t, tend = 0.0, ref["t_end"]
+    dt_r = p["cfl"] * b.dx[0] / p["chat"]
+    dtd = torch.zeros(1, dtype=torch.float64, device="cuda")
+    nsub = torch.zeros(1, dtype=torch.int32, device="cuda")
+    while t < tend * (1 - 1e-12):
+        oracle.fill_ghosts(b, oG)
+        sig = oracle.hydro_max_signal(b, oG, p["gamma"])
+        dt = min(p["cfl"] * b.dx[0] / sig, tend - t)
+        nn = max(1, int(np.ceil(dt / dt_r)))
+        if nn > p["nsub_max"]:  # the substep cap shrinks the step (Section 2.2.4)
+            nn = p["nsub_max"]
+            dt = nn * dt_r
+        dtd.fill_(dt)
+        nsub.fill_(nn)
+        ctx.hydro_step(b, G, hp, dt_dev=dtd)
+        ctx.rad_step(b, G, R, rp, dt_dev=dtd, nsub_dev=nsub)
+        st = oracle.rhd_step(b, oG, oR, p, dt=dt)
+        assert st["dt"] == dt and st["nsub"] == nn
+        t += dt
+    assert ctx.sync_status() == qb.QK_OK
+    g, r = host(G), host(R)
+    n, gi = b.n[0], b.ng
+    rho = g[0, gi, gi, gi:gi + n]
+    Tg = (g[4, gi, gi, gi:gi + n] - 0.5 * g[1, gi, gi, gi:gi + n] ** 2 / rho) * (p["gamma"] - 1) / rho
+    Tr = (r[0, gi, gi, gi:gi + n] / p["a_r"]) ** 0.25
+    T = ref["T"][gi:gi + n]
+    assert np.max(np.abs(Tg / T - 1)) < 2e-3
+    assert np.max(np.abs(Tr / T - 1)) < 2e-3
+    assert np.max(np.abs(Tg - Tr) / T) < 1e-5
+    for name, x, y in (("gas", g, oG), ("rad", r, oR)):
+        e = rel_linf(x, y, b)
+        assert np.all(e <= 1e-9), (name, e)
