@@ -189,6 +189,23 @@ qk_status quokka_batch_step(qk_ctx* ctx, const qk_box* boxes, int32_t nbox, void
  * if set. */
 qk_status quokka_batch_config(qk_ctx* ctx, int32_t* tile, int32_t* zc, double* tune_ms);
 
+/* quokka_hydro_step for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same step, the same kernels and the same bits, but the
+ * stage buffer and the flattening array live in a static device array of the
+ * library (128 MiB per GPU, held from the library's first context on that GPU
+ * until the process ends) instead of context scratch, and no measurement
+ * events are recorded.  Calls no hipMalloc, hipFree or allocating library
+ * routine.  Limit: 5 var_stride + var_stride elements (rounded up to 256
+ * bytes for the first part) must fit in 128 MiB: one 128^3 FP64 box with 4
+ * ghost layers (or 160^3 in FP32); larger boxes return QK_EINVAL.  Nothing in
+ * the array needs to start at zero (each call writes every element it
+ * reads).  Every call on one GPU, from any context, shares that GPU's array:
+ * calls that overlap in time on one GPU race. */
+qk_status quokka_hydro_step_noalloc(qk_ctx* ctx, const qk_box* box, void* U_gas, qk_precision prec,
+                                    const qk_hydro_params* hp, const double* dt_dev, double dt_in,
+                                    double* dt_next_dev, void* stream);
+
 /* ------------------------------------------------------------------------
  * AMR level synchronisation, refinement ratio 2 (Section 2.2: conservative
  * linear interpolation onto fine cells, conservative average-down, and the

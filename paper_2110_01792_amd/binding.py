@@ -21,7 +21,7 @@ EXPORTED = ("quokka_ctx_create", "quokka_ctx_destroy", "quokka_last_error", "quo
             "quokka_compute_dt", "quokka_hydro_step", "quokka_rad_step", "quokka_rhd_step", "quokka_batch_step",
             "quokka_sync_status", "quokka_newton_iter_max", "quokka_timing", "quokka_kernel_time", "quokka_batch_config",
             "quokka_hydro_step_reg", "quokka_average_down", "quokka_prolong", "quokka_reflux",
-            "quokka_rad_step_reg")
+            "quokka_rad_step_reg", "quokka_hydro_step_noalloc")
 K_HYDRO_STAGE, K_FLATTEN, K_RAD_STAGE, K_RAD_COUPLE, K_GHOST, K_BATCH = range(6)
 
 
@@ -95,6 +95,7 @@ def load():
         "quokka_compute_dt": (ctypes.c_int, [V, P(QkBox), V, ctypes.c_int, P(QkHydroParams), P(QkRadParams), V, V,
                                              P(D), V]),
         "quokka_hydro_step": (ctypes.c_int, [V, P(QkBox), V, ctypes.c_int, P(QkHydroParams), V, D, V, V]),
+        "quokka_hydro_step_noalloc": (ctypes.c_int, [V, P(QkBox), V, ctypes.c_int, P(QkHydroParams), V, D, V, V]),
         "quokka_rad_step": (ctypes.c_int, [V, P(QkBox), V, V, ctypes.c_int, P(QkRadParams), V, V, D, V]),
         "quokka_rhd_step": (ctypes.c_int, [V, P(QkBox), V, V, ctypes.c_int, P(QkRadParams), P(D), V]),
         "quokka_batch_step": (ctypes.c_int, [V, P(QkBox), I32, P(V), P(V), ctypes.c_int, P(QkHydroParams),
@@ -245,6 +246,13 @@ class Context:
         self._ok(self.lib.quokka_hydro_step(self.h, ctypes.byref(make_box(b, lay)), _ptr(Ug), _prec_of(Ug),
                                             ctypes.byref(hp), _ptr(dt_dev), float(dt), _ptr(dt_next_dev),
                                             _stream(stream)))
+
+    def hydro_step_noalloc(self, b, Ug, hp, dt_dev=None, dt=0.0, dt_next_dev=None, stream=None):
+        """quokka_hydro_step with the library's static scratch (allocates nothing)."""
+        lay = _check_state(Ug, b, 5)
+        self._ok(self.lib.quokka_hydro_step_noalloc(self.h, ctypes.byref(make_box(b, lay)), _ptr(Ug), _prec_of(Ug),
+                                                    ctypes.byref(hp), _ptr(dt_dev), float(dt), _ptr(dt_next_dev),
+                                                    _stream(stream)))
 
     # ---------------------------------------------------- AMR (ratio 2)
     def hydro_step_reg(self, b, Ug, hp, lo, hi, reg, dt=0.0, dt_dev=None, weight=1.0, stream=None):

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -105,9 +106,47 @@ void batch_cache_clear(BatchCache& c) {
   c = BatchCache();
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the no-allocation hydro step (quokka_hydro_step_noalloc): its
+// stage buffer and flattening array, sized for one 128^3 box (the paper's AMR
+// box size) with 4 ghost layers in FP64: 136^3 cells x (5 + 1) x 8 B =
+// 115 MiB.  Each GPU the library runs on holds its own copy at its own
+// address until the process ends; host code uses that address (looked up
+// once per device), never the symbol itself.
+// ---------------------------------------------------------------------------
+constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+bool g_scratch_done[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch` (the device must be current).
+void* scratch_address(int device, hipError_t* err) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  if (!g_scratch_done[device]) {
+    void* p = nullptr;
+    g_scratch_err[device] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_ptr[device] = g_scratch_err[device] == hipSuccess ? p : nullptr;
+    g_scratch_done[device] = true;
+  }
+  *err = g_scratch_err[device];
+  return g_scratch_ptr[device];
+}
+}  // namespace
+
 struct qk_ctx {
   int device = 0;
   std::string last_error;
+  void* noalloc_scratch = nullptr;   // this device's `scratch` (NULL: lookup failed)
+  hipError_t noalloc_err = hipSuccess;
   Scalars* sc = nullptr;
   Buf stage_g, stage_r, chi;
   Buf vflags;  // causality flags of the two radiation stages (kept zero between uses)
@@ -391,6 +430,48 @@ const double* resolve_dt(qk_ctx* ctx, const HostBox& hb, const S* U, double gamm
   return &ctx->sc->dt;
 }
 
+// One hydro step with the given stage buffer U1 (5 variables, U's layout)
+// and flattening array chi (one variable).  Allocates nothing; timed == false
+// records no measurement events.
+template <class S, class R>
+qk_status hydro_step_core(qk_ctx* ctx, const HostBox& hb, S* U, S* U1, R* chi, const qk_hydro_params* hp,
+                          const double* dt_dev, double dt_in, double* dt_next, hipStream_t s, const RegRec* rec,
+                          bool timed) {
+  double dtv;
+  const double* dtp = resolve_dt<S>(ctx, hb, U, hp->gamma, hp->cfl, dt_dev, dt_in, &dtv, s);
+  KernelTimer& T = ctx->timer;
+  auto tb = [&](int c) {
+    if (timed) T.begin(c, s);
+  };
+  auto te = [&](int c) {
+    if (timed) T.end(c, s);
+  };
+  if (hb.any_fixed) launch_ghost_copy<S>(hb, U1, U, 5, s);
+  tb(QK_K_FLATTEN);
+  launch_flatten<S, R>(hb, U, chi, hp->gamma, s);
+  te(QK_K_FLATTEN);
+  tb(QK_K_HYDRO_STAGE);
+  launch_stage<S, R, 1>(hb, U, U, U1, chi, hp->gamma, dtp, dtv, nullptr, &ctx->sc->err, hp->reconstruction, s, rec);
+  te(QK_K_HYDRO_STAGE);
+  tb(QK_K_GHOST);
+  launch_ghosts<S>(hb, U1, 5, s);
+  te(QK_K_GHOST);
+  tb(QK_K_FLATTEN);
+  launch_flatten<S, R>(hb, U1, chi, hp->gamma, s);
+  te(QK_K_FLATTEN);
+  tb(QK_K_HYDRO_STAGE);
+  launch_stage<S, R, 2>(hb, U1, U, U, chi, hp->gamma, dtp, dtv, dt_next ? &ctx->sc->smax_b : nullptr,
+                        &ctx->sc->err, hp->reconstruction, s, rec);
+  te(QK_K_HYDRO_STAGE);
+  tb(QK_K_GHOST);
+  launch_ghosts<S>(hb, U, 5, s);
+  te(QK_K_GHOST);
+  if (dt_next)
+    hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(64), 0, s, &ctx->sc->smax_b, hp->cfl, hb.d.dxmin, 0.0, 0,
+                       dt_next, (int32_t*)nullptr);
+  return hip_check(ctx, hipGetLastError(), "hydro step launch");
+}
+
 template <class S, class R>
 qk_status hydro_step_t(qk_ctx* ctx, const HostBox& hb, S* U, const qk_hydro_params* hp, const double* dt_dev,
                        double dt_in, double* dt_next, hipStream_t s, const RegRec* rec = nullptr) {
@@ -398,35 +479,8 @@ qk_status hydro_step_t(qk_ctx* ctx, const HostBox& hb, S* U, const qk_hydro_para
   const size_t ne = (size_t)hb.elems;
   if ((st = ensure(ctx, ctx->stage_g, 5 * ne * sizeof(S))) != QK_OK) return st;
   if ((st = ensure(ctx, ctx->chi, ne * sizeof(R))) != QK_OK) return st;
-  S* U1 = (S*)ctx->stage_g.p;
-  R* chi = (R*)ctx->chi.p;
-  double dtv;
-  const double* dtp = resolve_dt<S>(ctx, hb, U, hp->gamma, hp->cfl, dt_dev, dt_in, &dtv, s);
-  KernelTimer& T = ctx->timer;
-  if (hb.any_fixed) launch_ghost_copy<S>(hb, U1, U, 5, s);
-  T.begin(QK_K_FLATTEN, s);
-  launch_flatten<S, R>(hb, U, chi, hp->gamma, s);
-  T.end(QK_K_FLATTEN, s);
-  T.begin(QK_K_HYDRO_STAGE, s);
-  launch_stage<S, R, 1>(hb, U, U, U1, chi, hp->gamma, dtp, dtv, nullptr, &ctx->sc->err, hp->reconstruction, s, rec);
-  T.end(QK_K_HYDRO_STAGE, s);
-  T.begin(QK_K_GHOST, s);
-  launch_ghosts<S>(hb, U1, 5, s);
-  T.end(QK_K_GHOST, s);
-  T.begin(QK_K_FLATTEN, s);
-  launch_flatten<S, R>(hb, U1, chi, hp->gamma, s);
-  T.end(QK_K_FLATTEN, s);
-  T.begin(QK_K_HYDRO_STAGE, s);
-  launch_stage<S, R, 2>(hb, U1, U, U, chi, hp->gamma, dtp, dtv, dt_next ? &ctx->sc->smax_b : nullptr,
-                        &ctx->sc->err, hp->reconstruction, s, rec);
-  T.end(QK_K_HYDRO_STAGE, s);
-  T.begin(QK_K_GHOST, s);
-  launch_ghosts<S>(hb, U, 5, s);
-  T.end(QK_K_GHOST, s);
-  if (dt_next)
-    hipLaunchKernelGGL(finalize_dt_kernel, dim3(1), dim3(64), 0, s, &ctx->sc->smax_b, hp->cfl, hb.d.dxmin, 0.0, 0,
-                       dt_next, (int32_t*)nullptr);
-  return hip_check(ctx, hipGetLastError(), "hydro step launch");
+  return hydro_step_core<S, R>(ctx, hb, U, (S*)ctx->stage_g.p, (R*)ctx->chi.p, hp, dt_dev, dt_in, dt_next, s, rec,
+                               true);
 }
 
 qk_status read_status(qk_ctx* ctx, hipStream_t s) {
@@ -467,6 +521,7 @@ qk_status quokka_ctx_create(int device, qk_ctx** out) {
     return QK_ENOMEM;
   }
   (void)hipMemset(c->sc, 0, sizeof(Scalars));
+  c->noalloc_scratch = scratch_address(device, &c->noalloc_err);
   (void)hipDeviceSynchronize();
   *out = c;
   return QK_OK;
@@ -545,6 +600,33 @@ qk_status quokka_hydro_step(qk_ctx* ctx, const qk_box* box, void* U_gas, qk_prec
   hipStream_t s = (hipStream_t)stream;
   if (prec == QK_F64) return hydro_step_t<double, double>(ctx, hb, (double*)U_gas, hp, dt_dev, dt_in, dt_next_dev, s);
   return hydro_step_t<float, float>(ctx, hb, (float*)U_gas, hp, dt_dev, dt_in, dt_next_dev, s);
+}
+
+qk_status quokka_hydro_step_noalloc(qk_ctx* ctx, const qk_box* box, void* U_gas, qk_precision prec,
+                                    const qk_hydro_params* hp, const double* dt_dev, double dt_in,
+                                    double* dt_next_dev, void* stream) {
+  if (!ctx) return QK_EINVAL;
+  HostBox hb;
+  qk_status st;
+  if ((st = check_box(ctx, box, hb)) != QK_OK || (st = check_prec(ctx, prec)) != QK_OK ||
+      (st = check_hydro(ctx, hp)) != QK_OK)
+    return st;
+  if (!U_gas) return fail(ctx, QK_EINVAL, "state pointer is NULL");
+  if (!ctx->noalloc_scratch)
+    return fail(ctx, QK_EHIP, std::string("no-allocation scratch unavailable: ") + hipGetErrorString(ctx->noalloc_err));
+  const size_t es = prec == QK_F64 ? 8 : 4, ne = (size_t)hb.elems;
+  const size_t off_chi = (5 * ne * es + 255) & ~(size_t)255, need = off_chi + ne * es;
+  if (need > kNoAllocScratchBytes)
+    return fail(ctx, QK_EINVAL, "box needs " + std::to_string(need) + " bytes of scratch; the no-allocation step has " +
+                                    std::to_string(kNoAllocScratchBytes) + " (one 128^3 FP64 box with 4 ghost layers)");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ctx->noalloc_scratch;
+  if (prec == QK_F64)
+    return hydro_step_core<double, double>(ctx, hb, (double*)U_gas, (double*)base, (double*)(base + off_chi), hp,
+                                           dt_dev, dt_in, dt_next_dev, s, nullptr, false);
+  return hydro_step_core<float, float>(ctx, hb, (float*)U_gas, (float*)base, (float*)(base + off_chi), hp, dt_dev,
+                                       dt_in, dt_next_dev, s, nullptr, false);
 }
 
 qk_status quokka_sync_status(qk_ctx* ctx, void* stream) {
