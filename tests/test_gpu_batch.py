@@ -122,7 +122,11 @@ def test_batch_full_level_sampled_against_oracle(ctx):
 
 def test_batch_mixed_precision_error(ctx):
     """FP32 state and flux arithmetic (FP64 internal energy, exchange and stage
-    sums) against the FP64 oracle started from the same FP32-rounded data."""
+    sums) against the FP64 oracle started from the same FP32-rounded data:
+    per-variable normalised L1 within 1e-5, except the radiation flux, held to
+    2e-5.  F starts at zero and after two steps is a small field driven by
+    differences of E_r, so the FP32 rounding of the stored E_r dominates its
+    error (the same floor as on the 256^3 RHD workload)."""
     torch = pytest.importorskip("torch")
     boxes, Ugs, Urs, p, hp = inputs.batch_level(nbox=10, seed=33, edges=(8, 16, 24))
     Ugs = [inputs.to_f32_and_back(u) for u in Ugs]
@@ -132,17 +136,13 @@ def test_batch_mixed_precision_error(ctx):
     oR = [None if u is None else u.copy() for u in Urs]
     for _ in range(2):
         oracle.batch_step(boxes, oG, oR, hp["gamma"], hp["cfl"], p)
-    c = p["c"]
     for k, b in enumerate(boxes):
-        I = b.interior()
+        # per variable, sum |g - o| / sum |o| (momenta and F included)
         eg = norm_l1(gG[k], oG[k], b)
         assert np.all(eg <= 1e-5), (k, eg)
         if oR[k] is not None:
             er = norm_l1(gR[k], oR[k], b)
-            assert er[0] <= 1e-5, (k, er)
-            # F starts at zero and is bounded by c E_r: normalise by c sum(E_r)
-            ef = np.abs(gR[k][I][1:] - oR[k][I][1:]).sum(axis=(1, 2, 3)) / (c * np.abs(oR[k][I][0]).sum())
-            assert np.all(ef <= 1e-5), (k, er, ef)
+            assert er[0] <= 1e-5 and np.all(er[1:] <= 2e-5), (k, er)
 
 
 def test_batch_autotune_cache_file(tmp_path):
