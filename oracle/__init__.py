@@ -65,6 +65,7 @@ def _load():
         "oracle_hydro_rhs": (None, [P(_Box), _D, ctypes.c_double, ctypes.c_int, _D, P(_Stats)]),
         "oracle_hydro_step": (None, [P(_Box), _D, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                      P(_Stats)]),
+        "oracle_flatten_chi": (None, [P(_Box), _D, ctypes.c_double, _D]),
         "oracle_rad_rhs": (None, [P(_Box), _D, _D, P(_Rad), _D, P(_Stats)]),
         "oracle_rad_transport_substep": (None, [P(_Box), _D, _D, P(_Rad), ctypes.c_double, P(_Stats)]),
         "oracle_rad_stage": (None, [P(_Box), _D, _D, _D, P(_Rad), ctypes.c_double, _D, P(_Stats)]),
@@ -162,6 +163,15 @@ def hydro_rhs(b, U, gamma, recon=0):
     st = _Stats()
     _load().oracle_hydro_rhs(ctypes.byref(_box(b)), _ptr(U), float(gamma), int(recon), _ptr(L), ctypes.byref(st))
     return L, _stats(st)
+
+
+def flatten_chi(b, U, gamma):
+    """Flattening coefficient chi (one variable, box layout) of every cell of
+    the box grown by one cell along each active axis (ghosts of U must be filled)."""
+    _check(b, U, 5)
+    chi = np.zeros(U.shape[1:])
+    _load().oracle_flatten_chi(ctypes.byref(_box(b)), _ptr(U), float(gamma), _ptr(chi))
+    return chi
 
 
 def hydro_step(b, U, gamma, cfl, dt=0.0, recon=0):

@@ -278,6 +278,68 @@ static double chi_tilde(const double* P, const double* u, size_t o, ptrdiff_t s)
     for (int j = (J0); j < (J1); ++j)                               \
       for (int i = (I0); i < (I1); ++i)
 
+/* Shock flattening (Section 2.2.1; CW84 with the multidimensional extension
+ * of Miller & Colella 2002): per-axis coefficient chi_tilde over the cells
+ * whose +-2 neighbours exist, the minimum with the neighbour toward the
+ * higher pressure, then the minimum over axes, for cells [-1, n] of every
+ * active axis.  W holds the primitive variables (P in W[4]). */
+static void flatten_coeffs(const geo* g, const double* W, double* cht, double* chi) {
+  const size_t vs = g->vs;
+  const double* P = W + 4 * vs;
+  for (int d = 0; d < 3; ++d) {
+    double* c = cht + d * vs;
+    if (!g->act[d]) continue;
+    int lo[3] = {g->lo[0], g->lo[1], g->lo[2]}, hi[3] = {g->hi[0], g->hi[1], g->hi[2]};
+    lo[d] += 2;
+    hi[d] -= 2;
+    const double* u = W + (1 + d) * vs;
+    LOOP3(lo[2], hi[2], lo[1], hi[1], lo[0], hi[0]) {
+      const size_t o = IX(g, i, j, k);
+      c[o] = chi_tilde(P, u, o, g->st[d]);
+    }
+  }
+  {
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = g->act[d] ? -1 : 0;
+      hi[d] = g->act[d] ? g->n[d] + 1 : g->n[d];
+    }
+    LOOP3(lo[2], hi[2], lo[1], hi[1], lo[0], hi[0]) {
+      const size_t o = IX(g, i, j, k);
+      double x = 1.0;
+      for (int d = 0; d < 3; ++d) {
+        if (!g->act[d]) continue;
+        const ptrdiff_t s = g->st[d];
+        const double dp1 = P[o + s] - P[o - s];
+        const ptrdiff_t sh = (dp1 > 0.0) ? s : -s;
+        const double* c = cht + d * vs;
+        x = fmin(x, fmin(c[o], c[o + sh]));
+      }
+      chi[o] = x;
+    }
+  }
+}
+
+/* The flattening coefficient chi of Section 2.2.1 for every cell of the box
+ * grown by one cell along each active axis (0 elsewhere), from the
+ * conserved state U (ghosts filled). */
+void oracle_flatten_chi(const ob_box* b, const double* U, double gam, double* chi) {
+  geo g = make_geo(b);
+  const size_t vs = g.vs;
+  double* W = (double*)calloc(5 * vs, sizeof(double));
+  double* cht = (double*)calloc(3 * vs, sizeof(double));
+  memset(chi, 0, vs * sizeof(double));
+  LOOP3(g.lo[2], g.hi[2], g.lo[1], g.hi[1], g.lo[0], g.hi[0]) {
+    const size_t o = IX(&g, i, j, k);
+    double w[5];
+    to_prim(U, vs, o, gam, w);
+    for (int v = 0; v < 5; ++v) W[v * vs + o] = w[v];
+  }
+  flatten_coeffs(&g, W, cht, chi);
+  free(W);
+  free(cht);
+}
+
 static void record_region(const geo* g, const double* Fd, int nvar, const ob_region* r, double* reg, double w);
 
 static void hydro_rhs(const ob_box* b, const double* U, double gam, int recon, double* L, ob_stats* st,
@@ -313,41 +375,8 @@ static void hydro_rhs(const ob_box* b, const double* U, double gam, int recon, d
         if (!(W[o] > 0.0) || !(W[4 * vs + o] > 0.0)) ++neg;
       }
 
-  /* 2. shock flattening: per-axis coefficient, neighbour minimum toward the
-   *    higher pressure, then the minimum over axes. */
-  const double* P = W + 4 * vs;
-  for (int d = 0; d < 3; ++d) {
-    double* c = cht + d * vs;
-    if (!g.act[d]) continue;
-    int lo[3] = {g.lo[0], g.lo[1], g.lo[2]}, hi[3] = {g.hi[0], g.hi[1], g.hi[2]};
-    lo[d] += 2;
-    hi[d] -= 2;
-    const double* u = W + (1 + d) * vs;
-    LOOP3(lo[2], hi[2], lo[1], hi[1], lo[0], hi[0]) {
-      const size_t o = IX(&g, i, j, k);
-      c[o] = chi_tilde(P, u, o, g.st[d]);
-    }
-  }
-  {
-    int lo[3], hi[3];
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = g.act[d] ? -1 : 0;
-      hi[d] = g.act[d] ? g.n[d] + 1 : g.n[d];
-    }
-    LOOP3(lo[2], hi[2], lo[1], hi[1], lo[0], hi[0]) {
-      const size_t o = IX(&g, i, j, k);
-      double x = 1.0;
-      for (int d = 0; d < 3; ++d) {
-        if (!g.act[d]) continue;
-        const ptrdiff_t s = g.st[d];
-        const double dp1 = P[o + s] - P[o - s];
-        const ptrdiff_t sh = (dp1 > 0.0) ? s : -s;
-        const double* c = cht + d * vs;
-        x = fmin(x, fmin(c[o], c[o + sh]));
-      }
-      chi[o] = x;
-    }
-  }
+  /* 2. shock flattening */
+  flatten_coeffs(&g, W, cht, chi);
 
   /* 3-4. per axis: PPM of (rho, vx, vy, vz, P) with flattening, then HLLC at
    *      every face.  Face c-1/2 is stored at cell c. */

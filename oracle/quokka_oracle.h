@@ -69,6 +69,9 @@ double oracle_hydro_max_signal(const ob_box* b, const double* U, double gamma);
 void   oracle_hydro_rhs(const ob_box* b, const double* U, double gamma, int recon, double* L, ob_stats* st);
 void   oracle_hydro_step(const ob_box* b, double* U, double gamma, double cfl, double dt_in, int recon,
                          ob_stats* st);
+/* Flattening coefficient chi (Section 2.2.1) of every cell of the box grown by
+ * one cell along each active axis; 0 elsewhere; chi has the layout of one variable. */
+void   oracle_flatten_chi(const ob_box* b, const double* U, double gamma, double* chi);
 void   oracle_rad_rhs(const ob_box* b, const double* Ur, const double* Ug, const ob_rad* p, double* L, ob_stats* st);
 void   oracle_rad_transport_substep(const ob_box* b, double* Ur, const double* Ug, const ob_rad* p, double dt, ob_stats* st);
 /* One radiation RK stage over interior cells: Uout = Uin + dt L(Uin) if Ubase

@@ -291,3 +291,24 @@ def test_offsets_beyond_2_31_equal_a_small_box(ctx):
     del Ub
     assert np.array_equal(gb, gs[small.interior()])
     assert far == 1.0 / (gamma - 1.0)
+
+
+@pytest.mark.parametrize("case", ["x05_y03", "x03_y05", "upwind_neighbour"])
+def test_flattening_cases_of_the_pins(ctx, case):
+    """The states on which the oracle's flattening is pinned (a cell compressed
+    along x and y with different coefficients, 0.5 and 0.3, and a cell whose
+    own coefficient is 1 but whose high-pressure neighbour's is 0.5): one
+    step on the GPU against the oracle."""
+    from tests.test_oracle_components import FLAT, PROF_03, PROF_05, _flat_state
+    if case == "x05_y03":
+        args = (PROF_05[0], PROF_05[1], PROF_03[0], PROF_03[1])
+    elif case == "x03_y05":
+        args = (PROF_03[0], PROF_03[1], PROF_05[0], PROF_05[1])
+    else:
+        A = {3: 1.6 - 0.7 / 0.82, 4: 0.5, 5: 1.0, 6: 1.2, 7: 1.6, 8: 2.0, 9: 2.0}
+        u = {3: 0.0, 4: 0.1, 5: -0.1, 6: 0.0, 7: 0.0, 8: -0.1, 9: 0.0}
+        args = (A, u, FLAT[0], FLAT[1])
+    b, U, gamma = _flat_state(*args)
+    chi = oracle.flatten_chi(b, U, gamma)
+    assert chi[b.ng].min() < 0.6  # the flattening is active in this state
+    check(gpu_steps(ctx, b, U, gamma, 0.3, 1), oracle_steps(b, U, gamma, 0.3, 1), b, what=case)

@@ -4,6 +4,7 @@ import numpy as np
 import pytest
 
 import oracle
+from paper_2110_01792_amd import inputs
 from paper_2110_01792_amd.inputs import rad_params
 from tests.refsol import exact_riemann as er
 
@@ -236,3 +237,71 @@ def test_plm_mc_slope():
     assert abs(aL - 0.9) < 1e-15 and abs(aR - 1.1) < 1e-15
     aL, aR = oracle.plm_cell([0.0, 0.45, 1.0])  # slope |dc|/2 = 0.5
     assert abs(aL - 0.2) < 1e-15 and abs(aR - 0.7) < 1e-15
+
+
+# ----------------------------------------------------------- shock flattening
+def _flat_state(A, ux, B, uy, gamma=1.4, n=12):
+    """Box n x n x 1 (z inactive), rho = 1, P(i, j) = A[i] + B[j] - 1,
+    velocity (ux[i], uy[j], 0); A, B, ux, uy are dicts over interior indices
+    (missing entries: the nearest given value).  Ghost cells are filled."""
+    b = inputs.make_box((n, n, 1))
+    g = b.ng
+
+    def full(d):
+        ks = sorted(d)
+        return np.array([d[min(ks, key=lambda k: (abs(k - i), k))] for i in range(-g, n + g)])
+    Ai, Bj, ui, vj = full(A), full(B), full(ux), full(uy)
+    P = Ai[None, :] + Bj[:, None] - 1.0
+    vx = np.broadcast_to(ui[None, :], P.shape)
+    vy = np.broadcast_to(vj[:, None], P.shape)
+    U = np.zeros((5,) + b.shape)
+    U[0] = 1.0
+    U[1] = vx[None]
+    U[2] = vy[None]
+    U[4] = (P / (gamma - 1.0) + 0.5 * (vx * vx + vy * vy))[None]
+    oracle.fill_ghosts(b, U)
+    return b, U, gamma
+
+
+# profile with a compression at cell 6 whose jump ratio is z = dp1/dp2 = 0.8
+# (CW84 ramp: chi_tilde = 1 - (0.8 - 0.75)/0.1 = 0.5) and whose higher-pressure
+# neighbour (cell 7, expanding: du = u8 - u6 > 0) is not a shock
+PROF_05 = ({3: 1.0, 4: 1.0, 5: 1.1, 6: 1.5, 7: 1.9, 8: 2.0}, {4: 0.0, 5: 0.1, 6: 0.0, 7: -0.1, 8: 0.2})
+# the same with z = 0.82: chi_tilde = 1 - (0.82 - 0.75)/0.1 = 0.3
+PROF_03 = ({3: 1.0, 4: 1.0, 5: 1.09, 6: 1.5, 7: 1.91, 8: 2.0}, {4: 0.0, 5: 0.1, 6: 0.0, 7: -0.1, 8: 0.2})
+FLAT = ({0: 1.0}, {0: 0.0})
+
+
+@pytest.mark.parametrize("px,py,want", [(PROF_05, FLAT, 0.5), (FLAT, PROF_03, 0.3), (PROF_05, PROF_03, 0.3),
+                                        (PROF_03, PROF_05, 0.3)])
+def test_flattening_multidimensional_minimum(px, py, want):
+    """Section 2.2.1 flattening (CW84 coefficient, Miller & Colella's
+    multidimensional form): at a cell compressed along x with chi_tilde_x =
+    0.5 and along y with chi_tilde_y = 0.3 (values evaluated by hand from the
+    jump ratios), chi is the minimum over the axes, 0.3, whichever axis
+    carries which profile.  Other combinations give other values: the mean
+    0.4, the product 0.15, x alone 0.5 or 0.3 depending on the case.  A single
+    axis gives its own 1-D value."""
+    b, U, gamma = _flat_state(px[0], px[1], py[0], py[1])
+    chi = oracle.flatten_chi(b, U, gamma)
+    g = b.ng
+    assert chi[g, g + 6, g + 6] == pytest.approx(want, abs=1e-12)
+    # away from both profiles (and from the compression where the periodic
+    # box wraps the profile around, at cells 0 and 11) nothing is flattened
+    assert chi[g, g + 3, g + 3] == 1.0
+
+
+def test_flattening_takes_the_neighbour_toward_higher_pressure():
+    """The coefficient of a cell is the minimum of its own chi_tilde and that
+    of its neighbour toward the higher pressure.  Here cell 6 itself expands
+    (chi_tilde = 1), its high-pressure neighbour 7 has z = 0.8 (chi_tilde =
+    0.5) and its low-pressure neighbour 5 has z = 0.7/0.8536585 = 0.82
+    (chi_tilde = 0.3): chi(6) = 0.5, while taking both neighbours (or the
+    low one) would give 0.3 and taking none 1."""
+    A = {3: 1.6 - 0.7 / 0.82, 4: 0.5, 5: 1.0, 6: 1.2, 7: 1.6, 8: 2.0, 9: 2.0}
+    u = {3: 0.0, 4: 0.1, 5: -0.1, 6: 0.0, 7: 0.0, 8: -0.1, 9: 0.0}
+    b, U, gamma = _flat_state(A, u, *FLAT)
+    chi = oracle.flatten_chi(b, U, gamma)
+    g = b.ng
+    assert chi[g, g + 6, g + 6] == pytest.approx(0.5, abs=1e-12)
+    assert chi[g, g + 5, g + 5] == pytest.approx(0.3, abs=1e-9)  # cell 5's own coefficient shows
