@@ -9,13 +9,12 @@
  * code, header, constant or helper with the GPU library.
  *
  * Pins: the tests check every function against closed forms, invariants, the
- * paper's printed results or exact solutions.  One formula is parity
- * unpinned: the optical-depth factor min(1, 1/tau) of the radiation HLL
- * flux, which the paper names but does not write down (a reading).  The
- * radiation pressure tube of Section 3.3.1 runs with it active and holds the
- * paper's 0.2 per cent over the whole column, but gives the same error with
- * the factor off, so it does not fix the formula.  The causality rule that
- * switches the factor off is pinned by its defining properties.
+ * paper's printed results or exact solutions.  The optical-depth factor of
+ * the radiation HLL flux is named but not written down by the paper; its
+ * form here, min(1, 1/tau) on the dissipation of every radiation variable, is
+ * a reading.  That reading is pinned by the closed-form decay of grid-scale
+ * modes (where only the scaled dissipation acts), and the causality rule
+ * that switches the factor off by its defining properties.
  *
  * Array layout used by every entry point: one contiguous float64 array per
  * state, shape (nvar, nz+2ng, ny+2ng, nx+2ng), x fastest.  Gas state has

@@ -433,3 +433,40 @@ def test_rad_pressure_tube_whole_column_within_paper_bound(ctx):
     for name, x, y in (("gas", g, oG), ("rad", r, oR)):
         e = rel_linf(x, y, b)
         assert np.all(e <= 1e-9), (name, e)
+
+
+@pytest.mark.parametrize("var,tau", [(0, 4.0), (1, 4.0), (0, 100.0), (1, 100.0)])
+def test_grid_scale_modes_with_the_optical_depth_factor(ctx, var, tau):
+    """The checkerboard states on which the oracle's optical-depth factor is
+    pinned (only the scaled HLL dissipation acts on them): one radiation
+    substep (transport and coupling, kappa_P = 0) on the GPU against the
+    oracle, and the transported amplitude ratio against its closed form."""
+    from tests.test_oracle_rad import _uniform_slab
+    n = 16
+    b, Ug, p = _uniform_slab(n, tau)
+    c, ch = p["c"], p["chat"]
+    g = b.ng
+    sgn = (-1.0) ** np.arange(-g, n + g)
+    Ur = np.zeros((4,) + b.shape)
+    Ur[0] = 1.0
+    if var == 0:
+        Ur[0] = (1.0 + 0.01 * sgn)[None, None, :]
+    else:
+        Ur[1] = (0.1 * c * sgn)[None, None, :]
+    oracle.fill_ghosts(b, Ug)
+    oracle.fill_ghosts(b, Ur)
+    dt = p["cfl"] * b.dx[0] / ch
+    G, R = dev(Ug), dev(Ur)
+    ctx.rad_step(b, G, R, qb.rad_params(p), dt=dt)
+    assert ctx.sync_status() == qb.QK_OK
+    oG, oR = Ug.copy(), Ur.copy()
+    oracle.rad_transport_substep(b, oR, oG, p, dt)
+    oracle.exchange_all(b, oG, oR, p, dt)
+    oracle.fill_ghosts(b, oG)
+    oracle.fill_ghosts(b, oR)
+    check_pair((host(G), host(R)), (oG, oR), b, f"checkerboard var={var} tau={tau}")
+    if var == 0:  # E: the coupling leaves it (F = 0, kappa_P = 0)
+        z = 2.0 * min(1.0, 1.0 / tau) * (ch / np.sqrt(3.0)) * dt / b.dx[0]
+        a0 = Ur[0, g, g, g:g + n] - 1.0
+        a1 = host(R)[0, g, g, g:g + n] - 1.0
+        np.testing.assert_allclose(a1, (1.0 - z + 0.5 * z * z) * a0, rtol=1e-10, atol=1e-15)

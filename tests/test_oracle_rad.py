@@ -524,3 +524,95 @@ def test_causality_rule_in_rhd_steps():
     assert res[1][0] >= 1 and res[1][1:] == (0, 0, True), res
     assert res[0] == (0, 0, 0, True), res
     assert res[2][1] > 0 or not res[2][3], res
+
+
+# --------------------------- optical-depth factor and the diffusion limit
+def _uniform_slab(n, tau, chat=100.0, closure=1, tc=1):
+    """Periodic 1-D box of n cells on [0, 1], rho = 1, kappa_R = tau / dx
+    (tau = optical depth per cell), kappa_P = 0 (no exchange)."""
+    b = inputs.make_box((n, 1, 1), bc=inputs.PERIODIC)
+    kap = tau / b.dx[0]
+    p = inputs.rad_params(chat, kappa_P=0.0, kappa_R=kap, closure=closure, tau_correction=tc)
+    Ug = np.zeros((5,) + b.shape)
+    Ug[0] = 1.0
+    Ug[4] = 1.0 / (p["gamma"] - 1.0)
+    return b, Ug, p
+
+
+@pytest.mark.parametrize("var", [0, 1])
+@pytest.mark.parametrize("tau,tc", [(0.5, 1), (4.0, 1), (100.0, 1), (100.0, 0)])
+def test_optical_depth_factor_damps_grid_scale_modes(var, tau, tc):
+    """Section 2.2.2's optical-depth factor (reading: eps = min(1, 1/tau) on the
+    HLL dissipation of every radiation variable) against a closed form.  A
+    grid-scale checkerboard of E_r (var 0, F = 0) or of F_x (var 1, E_r
+    uniform) with the Eddington closure: every cell is an extremum, so PPM
+    falls back to the cell averages, the face average of the checkerboard
+    variable is uniform (no flux divergence from it) and only the HLL
+    dissipation acts, at rate lambda = 2 eps S / dx with S = chat / sqrt(3).
+    One SSP-RK2 transport substep then multiplies the checkerboard by
+    1 - z + z^2/2, z = lambda dt, exactly.  A factor missing, misplaced (one
+    variable only) or of another form (1/tau^2, 1/(1 + tau)) changes z."""
+    n = 16
+    b, Ug, p = _uniform_slab(n, tau, tc=tc)
+    c, ch = p["c"], p["chat"]
+    g = b.ng
+    sgn = (-1.0) ** np.arange(-g, n + g)
+    Ur = np.zeros((4,) + b.shape)
+    Ur[0] = 1.0
+    if var == 0:
+        Ur[0] = (1.0 + 0.01 * sgn)[None, None, :]
+    else:
+        Ur[1] = (0.1 * c * sgn)[None, None, :]
+    oracle.fill_ghosts(b, Ug)
+    oracle.fill_ghosts(b, Ur)
+    dt = p["cfl"] * b.dx[0] / ch
+    eps = min(1.0, 1.0 / tau) if tc else 1.0
+    z = 2.0 * eps * (ch / np.sqrt(3.0)) * dt / b.dx[0]
+    G = 1.0 - z + 0.5 * z * z
+    a0 = Ur[var, g, g, g:g + n] - (1.0 if var == 0 else 0.0)
+    oracle.rad_transport_substep(b, Ur, Ug, p, dt)
+    a1 = Ur[var, g, g, g:g + n] - (1.0 if var == 0 else 0.0)
+    np.testing.assert_allclose(a1, G * a0, rtol=1e-10, atol=1e-13 * np.abs(a0).max())
+    other = 1 - var  # the other variable is untouched
+    if other == 0:
+        np.testing.assert_allclose(Ur[0, g, g, g:g + n], 1.0, rtol=0, atol=1e-13)
+    else:
+        assert np.abs(Ur[1, g, g, g:g + n]).max() <= 1e-12 * c
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("tau", [5.0, 20.0, 100.0])
+def test_diffusion_limit_decay_of_a_smooth_mode(tau):
+    """Equilibrium-diffusion limit (tau per cell >> 1, Eddington closure): a
+    sinusoidal E_r mode with the diffusive flux F = -(c / (3 kappa rho)) dE/dx
+    decays at the rate D_eff k^2.  With the transport (SSP-RK2) split from the
+    implicit flux source F / (1 + rho kappa chat dt) (Sections 2.2.2-2.2.3),
+    the second transport stage moves F by cfl tau times its equilibrium value
+    and adds dt chat^2 / 6 to the diffusion coefficient D = chat / (3 kappa rho):
+    D_eff / D = 1 + cfl tau / 2 (the PPM faces of a smooth mode barely jump,
+    so the optical-depth factor does not enter).  Checked to 1 %."""
+    n, A = 64, 0.01
+    b, Ug, p = _uniform_slab(n, tau)
+    c, ch = p["c"], p["chat"]
+    kap = p["kappa_R"]
+    D = ch / (3.0 * kap)
+    g = b.ng
+    k = 2.0 * np.pi
+    xg = (np.arange(-g, n + g) + 0.5) * b.dx[0]
+    Ur = np.zeros((4,) + b.shape)
+    Ur[0] = (1.0 + A * np.sin(k * xg))[None, None, :]
+    Ur[1] = (-(c / (3.0 * kap)) * A * k * np.cos(k * xg))[None, None, :]
+    oracle.fill_ghosts(b, Ug)
+    oracle.fill_ghosts(b, Ur)
+    dt = p["cfl"] * b.dx[0] / ch
+    nst = int(0.05 / (D * k * k) / dt)
+    xs = xg[g:g + n]
+    amp = lambda U: 2.0 * np.mean((U[0, g, g, g:g + n] - 1.0) * np.sin(k * xs))
+    a0 = amp(Ur)
+    for _ in range(nst):
+        oracle.rad_transport_substep(b, Ur, Ug, p, dt)
+        oracle.exchange_all(b, Ug, Ur, p, dt)
+        oracle.fill_ghosts(b, Ug)
+        oracle.fill_ghosts(b, Ur)
+    Deff = -np.log(amp(Ur) / a0) / (k * k * nst * dt)
+    assert Deff / D == pytest.approx(1.0 + 0.5 * p["cfl"] * tau, rel=1e-2)
