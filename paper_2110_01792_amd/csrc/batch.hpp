@@ -108,7 +108,8 @@ __global__ __launch_bounds__(NT) void batch_stage_kernel(const BatchBox<S, R>* _
 template <class S, class R, int STAGE>
 __device__ __forceinline__ RadStageArgs<S, R> batch_rad_args(const BatchBox<S, R>& bb, const RadParamsDev& p,
                                                              const double* dt_ptr, const int32_t* nsub_ptr, int N,
-                                                             int sub, uint32_t* err, uint32_t* iter_max) {
+                                                             int sub, uint32_t* err, uint32_t* iter_max,
+                                                             const uint32_t* nthick) {
   RadStageArgs<S, R> a;
   a.Uin = STAGE == 1 ? bb.Ur : bb.Ur1;
   a.Ugh = STAGE == 1 ? nullptr : bb.Ur;
@@ -130,6 +131,7 @@ __device__ __forceinline__ RadStageArgs<S, R> batch_rad_args(const BatchBox<S, R
   a.vfl = bb.vf[STAGE - 1];
   a.vfl_clear = bb.vf[2 - STAGE];
   a.per = 0;
+  a.nthick = nthick;
   return a;
 }
 
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(NT, sizeof(S) == 4 ? 3 : 2) void batch_rad_kernel(c
                                                               const WorkItem* __restrict__ items, int nitems,
                                                               int* counter, RadParamsDev p, const double* dt_ptr,
                                                               const int32_t* nsub_ptr, int sub, uint32_t* err,
-                                                              uint32_t* iter_max) {
+                                                              uint32_t* iter_max, const uint32_t* nthick) {
   const int N = *nsub_ptr;
   if (sub >= N) return;
   __shared__ RadSmem<R, TX, TY, SPLIT> sm;
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(NT, sizeof(S) == 4 ? 3 : 2) void batch_rad_kernel(c
     if (it >= nitems) break;
     const WorkItem w = items[it];
     const RadStageArgs<S, R> a =
-        batch_rad_args<S, R, STAGE>(boxes[w.box], p, dt_ptr, nsub_ptr, N, sub, err, iter_max);
+        batch_rad_args<S, R, STAGE>(boxes[w.box], p, dt_ptr, nsub_ptr, N, sub, err, iter_max, nthick);
     itmax = max(itmax, rad_tile<S, R, TX, TY, NT, SPLIT, STAGE>(a, w.bx, w.by, w.bz, N, sm, bad, nfail));
     __syncthreads();
   }
@@ -183,7 +185,8 @@ __global__ __launch_bounds__(256) void batch_rad_fix_kernel(const BatchBox<S, R>
   uint32_t itmax = 0;
   for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n; t += gridDim.x * 256u) {
     const CellRef c = list[t];
-    const RadStageArgs<S, R> a = batch_rad_args<S, R, STAGE>(boxes[c.box], p, dt_ptr, nsub_ptr, N, sub, err, iter_max);
+    const RadStageArgs<S, R> a =
+        batch_rad_args<S, R, STAGE>(boxes[c.box], p, dt_ptr, nsub_ptr, N, sub, err, iter_max, count);
     itmax = max(itmax, rad_fix_cell<S, R, STAGE>(a, c.i, c.j, c.k, N, bad, nfail));
     a.vfl_clear[interior_index(a.b, c.i, c.j, c.k)] = 0;
   }

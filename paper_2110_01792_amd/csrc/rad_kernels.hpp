@@ -46,6 +46,9 @@ struct RadStageArgs {
   uint8_t* vfl;            // set to 1 by this stage at cells that violate |F| <= c E_r
   uint8_t* vfl_clear;      // flags of the other stage, cleared by this stage's fix-up
   int per;                 // bit d set: axis d is periodic (a face there joins both ends)
+  const uint32_t* nthick;  // number of thick cells of the step (NULL: not counted).  When it is
+                           // 0 no face has tau > 1, the factor is 1 everywhere, and the stage
+                           // skips the density halo and the optical depths altogether
 };
 
 // A cell of a thick-cell list: box index (0 for a single box) and cell.
@@ -252,7 +255,8 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
   auto& rhoP = sm.rhoP;
 
   const DevBox& b = a.b;
-  const RadParamsDev& p = a.p;
+  RadParamsDev p = a.p;
+  if (p.tau_correction && a.nthick && *a.nthick == 0u) p.tau_correction = 0;  // no thick face: eps = 1
   const int t = threadIdx.x, tx = t % TX, ty = t / TX;
   const int x0 = tbx * TX, y0 = tby * TY;
   const int tw = min(TX, b.n0 - x0), th = min(TY, b.n1 - y0);
