@@ -126,6 +126,7 @@ RAD_BYTES_STAGE1 = 72.0    # read E_r, F (32) + density (8), write 32   (FP64, p
 RAD_BYTES_STAGE2 = 168.0   # read Ur1, Ur (64) + gas (40), write Ur (32) + m, E (32)
 
 
+# with nsub_max = 10 substeps; the bench uses each run's mean substep count
 RHD_BYTES_PER_CELL_STEP = HYDRO_BYTES_PER_CELL_STEP + 10 * (RAD_BYTES_STAGE1 + RAD_BYTES_STAGE2)
 
 
@@ -147,9 +148,18 @@ def bench_rhd(ctx, qb, inputs, torch, steps, warmup, dtype, n=256, recon=0, clos
         step()
     ms = timed_steps(step, steps, torch)
     st = ctx.sync_status()
+    # Second pass: per-kernel HIP events, and the substep count N of every step
+    # (N = ceil(dt_h / dt_r) <= nsub_max; launches for substeps beyond N
+    # return at once and are not counted as work).
     ctx.newton_iter_max()
+    hp = qb.hydro_params(p["gamma"], p["cfl"], recon)
+    nsub = torch.zeros(1, dtype=torch.int32, device="cuda")
+    dtd = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ns = []
     ctx.timing(True)
     for _ in range(steps):
+        ctx.compute_dt(b, G, hp=hp, rp=rp, dt_dev=dtd, nsub_dev=nsub, host=False)
+        ns.append(int(nsub.item()))
         step()
     r1_ms, n1 = ctx.kernel_time(qb.K_RAD_STAGE)
     r2_ms, n2 = ctx.kernel_time(qb.K_RAD_COUPLE)
@@ -158,12 +168,18 @@ def bench_rhd(ctx, qb, inputs, torch, steps, warmup, dtype, n=256, recon=0, clos
     it = ctx.newton_iter_max()
     ncell = b.ncells
     scale = 1.0 if dtype == torch.float64 else 0.5
+    nact = max(sum(ns), 1)
+    nmean = sum(ns) / len(ns)
     out = {"ms_per_step": ms / steps, "cell_updates_per_s": ncell * steps / (ms * 1e-3), "status": int(st),
-           "rad_stage1_ms_avg": r1_ms / max(n1, 1), "rad_stage2_couple_ms_avg": r2_ms / max(n2, 1),
-           "hydro_stage_ms_avg": hs_ms / max(nh, 1), "launches": [n1, n2, nh], "newton_iter_max": it,
+           "rad_stage1_ms_avg": r1_ms / nact, "rad_stage2_couple_ms_avg": r2_ms / nact,
+           "hydro_stage_ms_avg": hs_ms / max(nh, 1), "launches": [n1, n2, nh], "active_substeps": nact,
+           "nsub_mean": nmean, "newton_iter_max": it,
            "ncells": ncell, "reconstruction": "PLM" if recon == 1 else "PPM",
            "closure": ("Levermore", "Eddington", "Minerbo")[closure], "source": bool(source)}
-    out["step_hbm_frac"] = RHD_BYTES_PER_CELL_STEP * scale * out["cell_updates_per_s"] / (HBM_PEAK_GBS * 1e9)
+    # algorithmic bytes of a step with the mean substep count of the run
+    rhd_bytes = HYDRO_BYTES_PER_CELL_STEP + nmean * (RAD_BYTES_STAGE1 + RAD_BYTES_STAGE2)
+    out["bytes_per_cell_step"] = rhd_bytes * scale
+    out["step_hbm_frac"] = rhd_bytes * scale * out["cell_updates_per_s"] / (HBM_PEAK_GBS * 1e9)
     out["rad_stage1_achieved_GBs"] = ncell * RAD_BYTES_STAGE1 * scale / (out["rad_stage1_ms_avg"] * 1e-3) / 1e9
     out["rad_stage2_achieved_GBs"] = ncell * RAD_BYTES_STAGE2 * scale / (out["rad_stage2_couple_ms_avg"] * 1e-3) / 1e9
     del G, R, J

@@ -47,13 +47,16 @@ __device__ __forceinline__ R mc_half_slope(R dl, R dr, R dc) {
 // Fourth-order interface value between a and b from the averages a-1 = am,
 // a, b, b+1 = bp.  A cell's right value and its right neighbour's left value
 // are the same expression on the same operands, so a sweep may carry it.
-template <class R>
+// FMA selects the fused multiply-add forms (one rounding where the separate
+// forms take two); the FP32 radiation reconstruction keeps the separate forms.
+template <class R, bool FMA = true>
 __device__ __forceinline__ R ppm_iface(R am, R a, R b, R bp) {
+  if constexpr (FMA) return fma(R(7.0 / 12.0), a + b, R(-1.0 / 12.0) * (am + bp));
   return R(7.0 / 12.0) * (a + b) - R(1.0 / 12.0) * (am + bp);
 }
 
 // PPM limiting of one cell from its unlimited interface values fl, fr.
-template <class R>
+template <class R, bool FMA = true>
 __device__ __forceinline__ void ppm_limit(R qm1, R q0, R qp1, R fl, R fr, R& aL, R& aR) {
   const R lo = rmin(qm1, rmin(q0, qp1));
   const R hi = rmax(qm1, rmax(q0, qp1));
@@ -63,19 +66,21 @@ __device__ __forceinline__ void ppm_limit(R qm1, R q0, R qp1, R fl, R fr, R& aL,
   const R h = mc_half_slope(dl, dr, dc);
   const bool ext = (fr - q0) * (q0 - fl) <= R(0);
   const R del = fr - fl;
-  const R a6 = R(6) * (q0 - R(0.5) * (fl + fr));
+  const R a6 = FMA ? R(6) * fma(R(-0.5), fl + fr, q0) : R(6) * (q0 - R(0.5) * (fl + fr));
   const R da = del * a6, d2 = del * del;
   const bool ovl = da > d2;
   const bool ovr = !ovl && (da < -d2);
-  const R fl2 = ovl ? R(3) * q0 - R(2) * fr : fl;
-  const R fr2 = ovr ? R(3) * q0 - R(2) * fl : fr;
+  const R q3 = R(3) * q0;
+  const R fl2 = ovl ? (FMA ? fma(R(-2), fr, q3) : q3 - R(2) * fr) : fl;
+  const R fr2 = ovr ? (FMA ? fma(R(-2), fl, q3) : q3 - R(2) * fl) : fr;
   aL = ext ? q0 - h : fl2;
   aR = ext ? q0 + h : fr2;
 }
 
-template <class R>
+template <class R, bool FMA = true>
 __device__ __forceinline__ void ppm(R qm2, R qm1, R q0, R qp1, R qp2, R& aL, R& aR) {
-  ppm_limit<R>(qm1, q0, qp1, ppm_iface<R>(qm2, qm1, q0, qp1), ppm_iface<R>(qm1, q0, qp1, qp2), aL, aR);
+  ppm_limit<R, FMA>(qm1, q0, qp1, ppm_iface<R, FMA>(qm2, qm1, q0, qp1), ppm_iface<R, FMA>(qm1, q0, qp1, qp2), aL,
+                    aR);
 }
 
 // PLM with the monotonized-central limiter (Section 2.2.1 alternative).
@@ -88,13 +93,19 @@ __device__ __forceinline__ void plm(R qm1, R q0, R qp1, R& aL, R& aR) {
 }
 
 // Reconstruction selected at run time (uniform across the launch).
-template <class R>
+template <class R, bool FMA = true>
 __device__ __forceinline__ void recon5(R qm2, R qm1, R q0, R qp1, R qp2, int recon, R& aL, R& aR) {
   if (recon == 1)
     plm<R>(qm1, q0, qp1, aL, aR);
   else
-    ppm<R>(qm2, qm1, q0, qp1, qp2, aL, aR);
+    ppm<R, FMA>(qm2, qm1, q0, qp1, qp2, aL, aR);
 }
+
+// Radiation reconstruction: fused forms in FP64 only (the FP32 radiation
+// flux is a small difference of E_r terms; its measured error against the
+// FP64 oracle grows with the fused forms).
+template <class R>
+constexpr bool kRadFma = sizeof(R) == 8;
 
 // ---------------------------------------------------------------------------
 // HLLC flux with PVRS wave speeds (Section 2.2.1; Toro ch. 10).  States are
@@ -125,7 +136,7 @@ __device__ __forceinline__ void hllc(const R* WL, const R* WR, const GasK<R>& k,
   const R cR = sqrt(g * pR * irR);
   const R rbar = R(0.5) * (rL + rR);
   const R cbar = R(0.5) * (cL + cR);
-  const R ps = rmax(R(0), R(0.5) * (pL + pR) - R(0.5) * (uR - uL) * rbar * cbar);
+  const R ps = rmax(R(0), fma(R(-0.5) * (uR - uL) * rbar, cbar, R(0.5) * (pL + pR)));
   // S_L = u_L - c_L q_L with q_L = 1 if p* <= p_L, else sqrt(1 + gq (p*/p_L - 1));
   // there c_L^2 q_L^2 = gamma (p_L + gq (p* - p_L)) / rho_L, so one square root
   // with the side's reciprocal density gives c_L q_L (likewise on the right).
@@ -133,12 +144,12 @@ __device__ __forceinline__ void hllc(const R* WL, const R* WR, const GasK<R>& k,
   R aL = cL, aR = cR;
   const bool shL = ps > pL, shR = ps > pR;
   if (__ballot(shL || shR)) {
-    if (shL) aL = sqrt(g * (pL + k.gq * (ps - pL)) * irL);
-    if (shR) aR = sqrt(g * (pR + k.gq * (ps - pR)) * irR);
+    if (shL) aL = sqrt(g * fma(k.gq, ps - pL, pL) * irL);
+    if (shR) aR = sqrt(g * fma(k.gq, ps - pR, pR) * irR);
   }
   const R SL = uL - aL;
   const R SR = uR + aR;
-  const R Ss = ((pR - pL) + rL * uL * (SL - uL) - rR * uR * (SR - uR)) / (rL * (SL - uL) - rR * (SR - uR));
+  const R Ss = fma(-rR * uR, SR - uR, fma(rL * uL, SL - uL, pR - pL)) / fma(rL, SL - uL, -rR * (SR - uR));
   // Side and branch exactly as the four-way selection on (S_L, S*, S_R):
   // 0 <= S_L: left flux; else 0 <= S*: left star; else 0 < S_R: right star;
   // else right flux.  Only the chosen side's energy and fluxes are formed.
@@ -146,19 +157,19 @@ __device__ __forceinline__ void hllc(const R* WL, const R* WR, const GasK<R>& k,
   const bool star = !(R(0) <= SL) && ((R(0) <= Ss) || (R(0) < SR));
   const R r = left ? rL : rR, u = left ? uL : uR, v = left ? vL : vR, w = left ? wL : wR;
   const R p = left ? pL : pR, S = left ? SL : SR;
-  const R E = p * k.inv_gm1 + R(0.5) * r * (u * u + (v * v + w * w));
-  const R f0 = r * u, f1 = r * u * u + p, f2 = r * u * v, f3 = r * u * w, f4 = u * (E + p);
+  const R E = fma(p, k.inv_gm1, R(0.5) * r * fma(u, u, v * v + w * w));
+  const R f0 = r * u, f1 = fma(f0, u, p), f2 = f0 * v, f3 = f0 * w, f4 = u * (E + p);
   // U*_4 = ph (E + (S* - u)(r S* + p / (S - u))) with ph = (S - u) / (S - S*);
   // ph / (S - u) = 1 / (S - S*), so one reciprocal serves both quotients.
   const R is = R(1) / (S - Ss);
   const R ph = (S - u) * is;
   const R Us0 = ph * r, Us1 = ph * (r * Ss), Us2 = ph * (r * v), Us3 = ph * (r * w);
-  const R Us4 = ph * (E + (Ss - u) * (r * Ss)) + (Ss - u) * (p * is);
-  F[0] = star ? f0 + S * (Us0 - r) : f0;
-  F[1] = star ? f1 + S * (Us1 - r * u) : f1;
-  F[2] = star ? f2 + S * (Us2 - r * v) : f2;
-  F[3] = star ? f3 + S * (Us3 - r * w) : f3;
-  F[4] = star ? f4 + S * (Us4 - E) : f4;
+  const R Us4 = fma(ph, fma(Ss - u, r * Ss, E), (Ss - u) * (p * is));
+  F[0] = star ? fma(S, Us0 - r, f0) : f0;
+  F[1] = star ? fma(S, Us1 - f0, f1) : f1;
+  F[2] = star ? fma(S, Us2 - r * v, f2) : f2;
+  F[3] = star ? fma(S, Us3 - r * w, f3) : f3;
+  F[4] = star ? fma(S, Us4 - E, f4) : f4;
 }
 
 // Signal speed |v| + c_s of one cell from its conserved state, in double

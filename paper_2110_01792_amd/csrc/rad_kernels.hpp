@@ -354,9 +354,10 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
       if (p.recon == 1) {
         plm<R>(w[v][1], w[v][2], w[v][3], L[v], Rr[v]);
       } else {
-        const R fl = decltype(carry)::value ? fzr[v] : ppm_iface<R>(w[v][0], w[v][1], w[v][2], w[v][3]);
-        fzr[v] = ppm_iface<R>(w[v][1], w[v][2], w[v][3], w[v][4]);
-        ppm_limit<R>(w[v][1], w[v][2], w[v][3], fl, fzr[v], L[v], Rr[v]);
+        const R fl =
+            decltype(carry)::value ? fzr[v] : ppm_iface<R, kRadFma<R>>(w[v][0], w[v][1], w[v][2], w[v][3]);
+        fzr[v] = ppm_iface<R, kRadFma<R>>(w[v][1], w[v][2], w[v][3], w[v][4]);
+        ppm_limit<R, kRadFma<R>>(w[v][1], w[v][2], w[v][3], fl, fzr[v], L[v], Rr[v]);
       }
     }
   };
@@ -467,7 +468,7 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const R* row = &Qp[v][yy + 3][xx + 1];
-            recon5<R>(row[0], row[1], row[2], row[3], row[4], p.recon, xL[v * XS + it], xR[v * XS + it]);
+            recon5<R, kRadFma<R>>(row[0], row[1], row[2], row[3], row[4], p.recon, xL[v * XS + it], xR[v * XS + it]);
           }
         }
       }
@@ -505,7 +506,7 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
         if (xx < tw && yy <= th) {
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            recon5<R>(Qp[v][yy + 1][xx + 3], Qp[v][yy + 2][xx + 3], Qp[v][yy + 3][xx + 3], Qp[v][yy + 4][xx + 3],
+            recon5<R, kRadFma<R>>(Qp[v][yy + 1][xx + 3], Qp[v][yy + 2][xx + 3], Qp[v][yy + 3][xx + 3], Qp[v][yy + 4][xx + 3],
                       Qp[v][yy + 5][xx + 3], p.recon, yL[v * YS + it], yR[v * YS + it]);
         }
       }
@@ -673,8 +674,8 @@ __device__ __forceinline__ void rad_flux_at(const RadStageArgs<S, R>& a, int d, 
   R sl[4], sr[4], tmp[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    recon5<R>(Q[0][v], Q[1][v], Q[2][v], Q[3][v], Q[4][v], p.recon, tmp[v], sl[v]);  // cell f-1, right
-    recon5<R>(Q[1][v], Q[2][v], Q[3][v], Q[4][v], Q[5][v], p.recon, sr[v], tmp[v]);  // cell f, left
+    recon5<R, kRadFma<R>>(Q[0][v], Q[1][v], Q[2][v], Q[3][v], Q[4][v], p.recon, tmp[v], sl[v]);  // cell f-1, right
+    recon5<R, kRadFma<R>>(Q[1][v], Q[2][v], Q[3][v], Q[4][v], Q[5][v], p.recon, sr[v], tmp[v]);  // cell f, left
   }
   R rl = R(0), rr = R(0);
   if (p.tau_correction) {
