@@ -258,6 +258,11 @@ __device__ __forceinline__ void closure_k2(R f2L, R f2R, int closure, R& kL, R& 
   } else if (closure == 2) {
     kL = ((R(3) - sqrt(f2L)) + R(3) * f2L) * R(0.2);
     kR = ((R(3) - sqrt(f2R)) + R(3) * f2R) * R(0.2);
+  } else if constexpr (kRadFma<R>) {
+    const R dl = R(2) + sqrt(fma(R(-3), f2L, R(4))), dr = R(2) + sqrt(fma(R(-3), f2R, R(4)));
+    const R q = R(3) / (dl * dr);
+    kL = q * dr;
+    kR = q * dl;
   } else {
     const R dl = R(2) + sqrt(R(4) - R(3) * f2L), dr = R(2) + sqrt(R(4) - R(3) * f2R);
     const R q = R(3) / (dl * dr);
@@ -289,9 +294,15 @@ __device__ __forceinline__ void eddington_row(R fx, R fy, R fz, R ff, R f2, R k,
   if (__ballot(over)) g = over ? k / ff : k;
   const R fd = d == 0 ? fx : (d == 1 ? fy : fz);
   const R gd = g * fd;
-  Tx = gd * fx + (d == 0 ? a : R(0));
-  Ty = gd * fy + (d == 1 ? a : R(0));
-  Tz = gd * fz + (d == 2 ? a : R(0));
+  if constexpr (kRadFma<R>) {  // fma(x, y, 0) = x y: the off-diagonal entries are unchanged
+    Tx = fma(gd, fx, d == 0 ? a : R(0));
+    Ty = fma(gd, fy, d == 1 ? a : R(0));
+    Tz = fma(gd, fz, d == 2 ? a : R(0));
+  } else {
+    Tx = gd * fx + (d == 0 ? a : R(0));
+    Ty = gd * fy + (d == 1 ? a : R(0));
+    Tz = gd * fz + (d == 2 ? a : R(0));
+  }
   Tdd = d == 0 ? Tx : (d == 1 ? Ty : Tz);
 }
 

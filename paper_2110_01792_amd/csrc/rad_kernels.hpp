@@ -88,10 +88,17 @@ __device__ __forceinline__ void rad_flux(R EL, R fLx, R fLy, R fLz, R ffL, R ER,
   const R FLd = d == 0 ? FLx : (d == 1 ? FLy : FLz);
   const R FRd = d == 0 ? FRx : (d == 1 ? FRy : FRz);
   const R h = R(0.5) * eps * S;
-  out[0] = R(0.5) * (ratio * FLd + ratio * FRd) - h * (ER - EL);
-  out[1] = R(0.5) * (cc * (EL * TLx) + cc * (ER * TRx)) - h * (FRx - FLx);
-  out[2] = R(0.5) * (cc * (EL * TLy) + cc * (ER * TRy)) - h * (FRy - FLy);
-  out[3] = R(0.5) * (cc * (EL * TLz) + cc * (ER * TRz)) - h * (FRz - FLz);
+  if constexpr (kRadFma<R>) {  // the left/right sums stay unfused (symmetric)
+    out[0] = fma(-h, ER - EL, R(0.5) * (ratio * FLd + ratio * FRd));
+    out[1] = fma(-h, FRx - FLx, R(0.5) * (cc * (EL * TLx) + cc * (ER * TRx)));
+    out[2] = fma(-h, FRy - FLy, R(0.5) * (cc * (EL * TLy) + cc * (ER * TRy)));
+    out[3] = fma(-h, FRz - FLz, R(0.5) * (cc * (EL * TLz) + cc * (ER * TRz)));
+  } else {
+    out[0] = R(0.5) * (ratio * FLd + ratio * FRd) - h * (ER - EL);
+    out[1] = R(0.5) * (cc * (EL * TLx) + cc * (ER * TRx)) - h * (FRx - FLx);
+    out[2] = R(0.5) * (cc * (EL * TLy) + cc * (ER * TRy)) - h * (FRy - FLy);
+    out[3] = R(0.5) * (cc * (EL * TLz) + cc * (ER * TRz)) - h * (FRz - FLz);
+  }
 }
 
 // Face between cell "l" (reconstructed right state aL*) and cell "r": choose
