@@ -17,6 +17,7 @@ namespace qk {
 
 struct RadParamsDev {
   double c, chat, a_r, kappa_P, kappa_R, gamma, alpha_cv, newton_tol;
+  double c_over_chat, chat_over_c, inv_c_chat;  // c / chat, chat / c, 1 / (chat c): formed once on the host
   int newton_max_iter, closure, tau_correction, eos, recon;
   const void* src;  // NULL or per-cell radiation source rate j (state precision)
 };
@@ -145,7 +146,7 @@ __device__ __forceinline__ int exchange(const RadParamsDev& p, double dt, double
                                         bool& fail) {
   const double rho = gas[0];
   const double c = p.c, ch = p.chat;
-  const double coc = c / ch;
+  const double coc = p.c_over_chat;
   const double inv_rho = 1.0 / rho;
   const double Ek0 = 0.5 * ((gas[1] * gas[1] + gas[2] * gas[2]) + gas[3] * gas[3]) * inv_rho;
   const double Eg0 = gas[4] - Ek0;
@@ -189,7 +190,7 @@ __device__ __forceinline__ int exchange(const RadParamsDev& p, double dt, double
   }
   fail = fail || !conv;
   const double inv_fac = 1.0 / (1.0 + rho * p.kappa_R * ch * dt);
-  const double inv_cc = 1.0 / (ch * c);
+  const double inv_cc = p.inv_c_chat;
   double m[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -204,7 +205,7 @@ __device__ __forceinline__ int exchange(const RadParamsDev& p, double dt, double
   gas[2] = m[1];
   gas[3] = m[2];
   gas[4] = Eg + (Ek0 + dEk);
-  rad[0] = Er - (ch / c) * dEk;
+  rad[0] = Er - p.chat_over_c * dEk;
   return it;
 }
 
