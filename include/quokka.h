@@ -173,7 +173,10 @@ qk_status quokka_rhd_step(qk_ctx* ctx, const qk_box* box, void* U_gas, void* U_r
  * advanced with it; U_rad[i] == NULL marks a hydro-only box.  Each RK stage of
  * every box runs in one persistent launch over a (box, tile) work list; the
  * whole step is captured once per box list into a HIP graph and replayed.
- * boxes, U_gas and U_rad are host arrays of length nbox. */
+ * boxes, U_gas and U_rad are host arrays of length nbox.  Replays share the
+ * context's scratch: a call on another stream than the previous call's waits
+ * on the device for the previous replay, and a call with a different box list
+ * (or state pointers) first waits on the host for it, then re-plans. */
 qk_status quokka_batch_step(qk_ctx* ctx, const qk_box* boxes, int32_t nbox, void* const* U_gas,
                             void* const* U_rad, qk_precision prec, const qk_hydro_params* hp,
                             const qk_rad_params* rp, double* dt_host, void* stream);

@@ -87,6 +87,7 @@ struct BatchCache {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t cs = nullptr;
+  hipEvent_t done = nullptr;  // recorded after every graph launch, on the caller's stream of that call
   void* pool = nullptr;
   size_t pool_bytes = 0;
   void* meta = nullptr;
@@ -103,6 +104,7 @@ void batch_cache_clear(BatchCache& c) {
   if (c.pool) (void)hipFree(c.pool);
   if (c.meta) (void)hipFree(c.meta);
   if (c.cs) (void)hipStreamDestroy(c.cs);
+  if (c.done) (void)hipEventDestroy(c.done);
   c = BatchCache();
 }
 

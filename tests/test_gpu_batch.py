@@ -145,6 +145,36 @@ def test_batch_mixed_precision_error(ctx):
             assert er[0] <= 1e-5 and np.all(er[1:] <= 2e-5), (k, er)
 
 
+def test_batch_alternating_lists_on_side_streams(ctx):
+    """Two box lists stepped alternately on two non-default streams with no
+    host synchronisation between calls: every call re-plans (the cached graph
+    belongs to the other list) while the previous replay may still run, and a
+    call on the other stream must wait for it.  After five calls each level
+    equals the oracle's level steps."""
+    torch = pytest.importorskip("torch")
+    levels = []
+    for seed, nbox, edges in ((41, 9, (8, 16, 24)), (42, 6, (8, 16))):
+        boxes, Ugs, Urs, p, hp = inputs.batch_level(nbox=nbox, seed=seed, edges=edges)
+        levels.append(dict(boxes=boxes, p=p, hp=hp, G=[dev(u) for u in Ugs],
+                           R=[None if u is None else dev(u) for u in Urs],
+                           oG=[u.copy() for u in Ugs], oR=[None if u is None else u.copy() for u in Urs]))
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    order = [(0, 0), (1, 0), (0, 1), (1, 1), (0, 0)]
+    for lv, si in order:
+        L, s = levels[lv], streams[si]
+        with torch.cuda.stream(s):
+            ctx.batch_step(L["boxes"], L["G"], L["R"], qb.hydro_params(L["hp"]["gamma"], L["hp"]["cfl"]),
+                           qb.rad_params(L["p"]), host_dt=False, stream=s.cuda_stream)
+        oracle.batch_step(L["boxes"], L["oG"], L["oR"], L["hp"]["gamma"], L["hp"]["cfl"], L["p"])
+    for s in streams:
+        s.synchronize()
+    assert ctx.sync_status() == qb.QK_OK
+    for lv, L in enumerate(levels):
+        compare(L["boxes"], [host(g) for g in L["G"]], [None if r is None else host(r) for r in L["R"]],
+                L["oG"], L["oR"], what=f"level {lv}")
+
+
 def test_batch_autotune_cache_file(tmp_path):
     """The autotuner writes its choice to the JSON file named by QK_TUNE_CACHE
     and a new context reads it back."""
