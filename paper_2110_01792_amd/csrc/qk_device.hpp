@@ -28,6 +28,61 @@ template <class R> __device__ __forceinline__ R rmin(R a, R b) { return fmin(a, 
 template <class R> __device__ __forceinline__ R rmax(R a, R b) { return fmax(a, b); }
 
 // ---------------------------------------------------------------------------
+// Reciprocal, quotient and square root by Newton's iteration from the
+// hardware estimates (v_rcp, v_rsq), for operands the update keeps in the
+// normal range (densities, pressures, sound speeds, wave-speed gaps,
+// radiation energies): no range scaling and no special-value handling, on
+// which the IEEE expansions spend about half their instructions.
+//   rcp_nz(b): steps r <- r + r (1 - b r) (two in FP64 from a 2^-24
+//     estimate, one in FP32 from a 1-ulp estimate); b finite, nonzero, |b|
+//     and 1/|b| normal.  b = 0 gives NaN (IEEE: inf).
+//   div_nz(a, b): q = a r, then one residual correction q + r (a - b q).
+//   sqrt_pos(x): Goldschmidt's coupled iteration for s ~ sqrt(x) and
+//     h ~ 1/(2 sqrt(x)) from g = rsq(x), then residual corrections
+//     s + h (x - s s); x > 0 normal.  x = 0 gives NaN (sqrt_nn handles it).
+// Each result is the correctly rounded one or within one unit in the last
+// place of it.
+// ---------------------------------------------------------------------------
+template <class R>
+__device__ __forceinline__ R rcp_nz(R b) {
+  if constexpr (sizeof(R) == 8) {
+    R r = __builtin_amdgcn_rcp(b);
+    r = fma(fma(-b, r, R(1)), r, r);
+    return fma(fma(-b, r, R(1)), r, r);
+  } else {
+    const R r = __builtin_amdgcn_rcpf(b);
+    return fma(fma(-b, r, R(1)), r, r);
+  }
+}
+template <class R>
+__device__ __forceinline__ R div_nz(R a, R b) {
+  const R r = rcp_nz(b), q = a * r;
+  return fma(fma(-b, q, a), r, q);
+}
+template <class R>
+__device__ __forceinline__ R sqrt_pos(R x) {
+  if constexpr (sizeof(R) == 8) {
+    const R g = __builtin_amdgcn_rsq(x);
+    R s = x * g, h = R(0.5) * g;
+    const R e = fma(-h, s, R(0.5));
+    s = fma(s, e, s);
+    h = fma(h, e, h);
+    s = fma(fma(-s, s, x), h, s);
+    return fma(fma(-s, s, x), h, s);
+  } else {
+    const R g = __builtin_amdgcn_rsqf(x);
+    const R s = x * g, h = R(0.5) * g;
+    return fma(fma(-s, s, x), h, s);
+  }
+}
+// sqrt_pos extended to x = 0 (returns 0).
+template <class R>
+__device__ __forceinline__ R sqrt_nn(R x) {
+  const R s = sqrt_pos(x);
+  return x > R(0) ? s : R(0);
+}
+
+// ---------------------------------------------------------------------------
 // PPM of one cell from the five cell averages centred on it (Section 2.2.1):
 // symmetric fourth-order interface values, clamp to the neighbour range,
 // CW84 extremum test with a monotonized-central linear fallback, CW84
@@ -131,9 +186,9 @@ __device__ __forceinline__ void hllc(const R* WL, const R* WR, const GasK<R>& k,
   const R rL = WL[0], uL = WL[1], vL = WL[2], wL = WL[3], pL = WL[4];
   const R rR = WR[0], uR = WR[1], vR = WR[2], wR = WR[3], pR = WR[4];
   const R g = k.g;
-  const R irL = R(1) / rL, irR = R(1) / rR;
-  const R cL = sqrt(g * pL * irL);
-  const R cR = sqrt(g * pR * irR);
+  const R irL = rcp_nz(rL), irR = rcp_nz(rR);
+  const R cL = sqrt_pos(g * pL * irL);
+  const R cR = sqrt_pos(g * pR * irR);
   const R rbar = R(0.5) * (rL + rR);
   const R cbar = R(0.5) * (cL + cR);
   const R ps = rmax(R(0), fma(R(-0.5) * (uR - uL) * rbar, cbar, R(0.5) * (pL + pR)));
@@ -144,12 +199,12 @@ __device__ __forceinline__ void hllc(const R* WL, const R* WR, const GasK<R>& k,
   R aL = cL, aR = cR;
   const bool shL = ps > pL, shR = ps > pR;
   if (__ballot(shL || shR)) {
-    if (shL) aL = sqrt(g * fma(k.gq, ps - pL, pL) * irL);
-    if (shR) aR = sqrt(g * fma(k.gq, ps - pR, pR) * irR);
+    if (shL) aL = sqrt_pos(g * fma(k.gq, ps - pL, pL) * irL);
+    if (shR) aR = sqrt_pos(g * fma(k.gq, ps - pR, pR) * irR);
   }
   const R SL = uL - aL;
   const R SR = uR + aR;
-  const R Ss = fma(-rR * uR, SR - uR, fma(rL * uL, SL - uL, pR - pL)) / fma(rL, SL - uL, -rR * (SR - uR));
+  const R Ss = div_nz(fma(-rR * uR, SR - uR, fma(rL * uL, SL - uL, pR - pL)), fma(rL, SL - uL, -rR * (SR - uR)));
   // Side and branch exactly as the four-way selection on (S_L, S*, S_R):
   // 0 <= S_L: left flux; else 0 <= S*: left star; else 0 < S_R: right star;
   // else right flux.  Only the chosen side's energy and fluxes are formed.
@@ -160,9 +215,12 @@ __device__ __forceinline__ void hllc(const R* WL, const R* WR, const GasK<R>& k,
   const R E = fma(p, k.inv_gm1, R(0.5) * r * fma(u, u, v * v + w * w));
   const R f0 = r * u, f1 = fma(f0, u, p), f2 = f0 * v, f3 = f0 * w, f4 = u * (E + p);
   // U*_4 = ph (E + (S* - u)(r S* + p / (S - u))) with ph = (S - u) / (S - S*);
-  // ph / (S - u) = 1 / (S - S*), so one reciprocal serves both quotients.
-  const R is = R(1) / (S - Ss);
-  const R ph = (S - u) * is;
+  // ph / (S - u) = 1 / (S - S*), so one reciprocal serves both quotients
+  // (div_nz forms the same reciprocal; S - S* is nonzero wherever a star state
+  // is chosen).  ph is a corrected quotient, so it is exactly 1 where S* = u,
+  // as at a stationary contact.
+  const R is = rcp_nz(S - Ss);
+  const R ph = div_nz(S - u, S - Ss);
   const R Us0 = ph * r, Us1 = ph * (r * Ss), Us2 = ph * (r * v), Us3 = ph * (r * w);
   const R Us4 = fma(ph, fma(Ss - u, r * Ss, E), (Ss - u) * (p * is));
   F[0] = star ? fma(S, Us0 - r, f0) : f0;
@@ -178,11 +236,11 @@ __device__ __forceinline__ void hllc(const R* WL, const R* WR, const GasK<R>& k,
 // and c_s^2 = gamma P / rho.  Every dt reduction uses this function.
 __device__ __forceinline__ double signal_speed(const double* q, double gamma, double gm1, bool& bad) {
   const double rho = q[0];
-  const double inv = 1.0 / rho;
+  const double inv = rcp_nz(rho);
   const double m2 = (q[1] * q[1] + q[2] * q[2]) + q[3] * q[3];
   const double P = gm1 * (q[4] - 0.5 * m2 * inv);
   bad = bad || !(rho > 0.0) || !(P > 0.0);
-  return sqrt(m2) * inv + sqrt(gamma * P * inv);
+  return sqrt_nn(m2) * inv + sqrt_pos(gamma * P * inv);
 }
 
 // Conserved -> primitive.  The internal energy E - |m|^2/(2 rho) is always
@@ -190,7 +248,7 @@ __device__ __forceinline__ double signal_speed(const double* q, double gamma, do
 template <class R>
 __device__ __forceinline__ void cons_to_prim(double rho, double mx, double my, double mz, double E, double gm1,
                                              R* W, bool& bad) {
-  const double inv = 1.0 / rho;
+  const double inv = rcp_nz(rho);
   const double ek = 0.5 * ((mx * mx + my * my) + mz * mz) * inv;
   const double P = gm1 * (E - ek);
   const R ri = R(inv);
@@ -258,14 +316,14 @@ __device__ __forceinline__ void closure_k2(R f2L, R f2R, int closure, R& kL, R& 
   } else if (closure == 2) {
     kL = ((R(3) - sqrt(f2L)) + R(3) * f2L) * R(0.2);
     kR = ((R(3) - sqrt(f2R)) + R(3) * f2R) * R(0.2);
-  } else if constexpr (kRadFma<R>) {
-    const R dl = R(2) + sqrt(fma(R(-3), f2L, R(4))), dr = R(2) + sqrt(fma(R(-3), f2R, R(4)));
-    const R q = R(3) / (dl * dr);
+  } else if constexpr (kRadFma<R>) {  // 4 - 3 f2 in [1, 4], (2 + s_L)(2 + s_R) in [9, 16]
+    const R dl = R(2) + sqrt_pos(fma(R(-3), f2L, R(4))), dr = R(2) + sqrt_pos(fma(R(-3), f2R, R(4)));
+    const R q = div_nz(R(3), dl * dr);
     kL = q * dr;
     kR = q * dl;
   } else {
-    const R dl = R(2) + sqrt(R(4) - R(3) * f2L), dr = R(2) + sqrt(R(4) - R(3) * f2R);
-    const R q = R(3) / (dl * dr);
+    const R dl = R(2) + sqrt_pos(R(4) - R(3) * f2L), dr = R(2) + sqrt_pos(R(4) - R(3) * f2R);
+    const R q = div_nz(R(3), dl * dr);
     kL = q * dr;
     kR = q * dl;
   }

@@ -82,7 +82,7 @@ __device__ __forceinline__ void rad_flux(R EL, R fLx, R fLy, R fLz, R ffL, R ER,
   closure_k2<R>(f2L, f2R, closure, kL, kR);
   eddington_row<R>(fLx, fLy, fLz, ffL, f2L, kL, d, TLx, TLy, TLz, dL);
   eddington_row<R>(fRx, fRy, fRz, ffR, f2R, kR, d, TRx, TRy, TRz, dR);
-  const R S = chat * sqrt(rmax(dL, dR));
+  const R S = chat * sqrt_nn(rmax(dL, dR));  // T_dd = 0 for a beam across the axis
   const R cEL = c * EL, cER = c * ER;
   const R FLx = cEL * fLx, FLy = cEL * fLy, FLz = cEL * fLz;
   const R FRx = cER * fRx, FRy = cER * fRy, FRz = cER * fRz;
@@ -132,7 +132,7 @@ __device__ __forceinline__ void rad_face(const R* sl, const R* sr, const Cells& 
     // cell where the causality rule switched the correction off.
     const R tau = face_tau<R>(dxd, R(p.kappa_R), rhol, rhor);
     const bool thick = !tau_off && tau > R(1);
-    if (__ballot(thick)) eps = thick ? R(1) / tau : R(1);
+    if (__ballot(thick)) eps = thick ? rcp_nz(tau) : R(1);
   }
   rad_flux<R>(L[0], L[1], L[2], L[3], ffl, Rr[0], Rr[1], Rr[2], Rr[3], ffr, d, p.closure, c, chat, ratio, cc, eps, out);
 }
@@ -147,12 +147,12 @@ __device__ __forceinline__ int exchange(const RadParamsDev& p, double dt, double
   const double rho = gas[0];
   const double c = p.c, ch = p.chat;
   const double coc = p.c_over_chat;
-  const double inv_rho = 1.0 / rho;
+  const double inv_rho = rcp_nz(rho);
   const double Ek0 = 0.5 * ((gas[1] * gas[1] + gas[2] * gas[2]) + gas[3] * gas[3]) * inv_rho;
   const double Eg0 = gas[4] - Ek0;
   const double Er0 = rad[0];
   const double Etot = Eg0 + coc * (Er0 + S);
-  const double inv_Etot = 1.0 / Etot;
+  const double inv_Etot = rcp_nz(Etot);
   const double k1 = dt * rho * p.kappa_P * ch;         // dR/d(a_r T^4 - E_r)
   const double dFG_dEr = -c * dt * rho * p.kappa_P;
   const double dFR_dEr = 1.0 + ch * dt * rho * p.kappa_P;
@@ -181,15 +181,15 @@ __device__ __forceinline__ int exchange(const RadParamsDev& p, double dt, double
     }
     const double dFG_dEg = 1.0 + coc * dRdEg;
     const double dFR_dEg = -dRdEg;
-    const double inv_g = 1.0 / dFG_dEg;
+    const double inv_g = rcp_nz(dFG_dEg);
     const double eta = -dFR_dEg * inv_g;
-    const double dEr = -(FR + eta * FG) / (dFR_dEr + eta * dFG_dEr);
+    const double dEr = div_nz(-(FR + eta * FG), dFR_dEr + eta * dFG_dEr);
     const double dEg = -(FG + dEr * dFG_dEr) * inv_g;
     Eg += dEg;
     Er += dEr;
   }
   fail = fail || !conv;
-  const double inv_fac = 1.0 / (1.0 + rho * p.kappa_R * ch * dt);
+  const double inv_fac = rcp_nz(1.0 + rho * p.kappa_R * ch * dt);
   const double inv_cc = p.inv_c_chat;
   double m[3];
 #pragma unroll
@@ -327,7 +327,7 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
   auto to_q = [&](const double* u, R* Q, bool& flag) {
     const double E = u[0];
     const R Er = R(E);
-    const R inv = R(1) / (c * Er);
+    const R inv = rcp_nz(c * Er);  // E_r > 0
     Q[0] = Er;
     Q[1] = R(u[1]) * inv;
     Q[2] = R(u[2]) * inv;
@@ -674,7 +674,7 @@ __device__ __forceinline__ void rad_flux_at(const RadStageArgs<S, R>& a, int d, 
     const S* src = src_at(a.Uin, a.Ugh, b, ii, jj, kk);
     const int64_t o = cell(b, ii, jj, kk);
     const R Er = R(double(src[o]));
-    const R inv = R(1) / (c * Er);
+    const R inv = rcp_nz(c * Er);  // E_r > 0
     Q[s][0] = Er;
 #pragma unroll
     for (int v = 1; v < 4; ++v) Q[s][v] = R(double(src[o + v * b.vs])) * inv;
