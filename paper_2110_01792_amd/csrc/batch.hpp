@@ -9,8 +9,10 @@
 // Work lists are sorted largest tile first.  Tile families: 8 x 8 columns on
 // 64 threads and 16 x 16 on 256 (x and y sweeps share LDS buffers), and the
 // single-box shape 16 x 14 on 256 threads with separate x/y buffers (every
-// sweep phase one item per thread, three barriers per plane).  Ghost cells of a stage buffer are
-// read from the box's own fixed ghosts (ghost-source pointer), so no copies.
+// sweep phase one item per thread, three barriers per plane).  The flattening
+// pass runs on the single-box flattening tile (32 x 30 on 1024 threads) in
+// every family.  Ghost cells of a stage buffer are read from the box's own
+// fixed ghosts (ghost-source pointer), so no copies.
 #pragma once
 #include "rad_kernels.hpp"
 
