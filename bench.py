@@ -481,6 +481,10 @@ def main():
         "traffic_unit": "HBM bytes per stage launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated; "
                         "null when the kernel sources differ from those the counters were taken on)",
         "kernel": "stage_kernel<double,double,1|2> (fused hydro RK stage, 16x14 tiles)",
+        # the counted bytes over the same launch time: the HBM fraction the
+        # stage actually moves (halo re-reads included)
+        "traffic_frac": (round(measured_traffic() / (h64["stage_ms_avg"] * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)
+                         if measured_traffic() is not None else None),
         "bytes_per_cell_launch": HYDRO_BYTES_PER_CELL_STEP / 2,
         "cells_per_launch": h64["ncells"],
         "stage_ms_avg": round(h64["stage_ms_avg"], 4),
