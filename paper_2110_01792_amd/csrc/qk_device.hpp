@@ -26,6 +26,15 @@ __device__ __forceinline__ int64_t cell(const DevBox& b, int i, int j, int k) {
 
 template <class R> __device__ __forceinline__ R rmin(R a, R b) { return fmin(a, b); }
 template <class R> __device__ __forceinline__ R rmax(R a, R b) { return fmax(a, b); }
+// min(max(x, lo), hi) for lo <= hi; in FP32 one median-of-three instruction
+// (the same value for finite operands).
+template <class R>
+__device__ __forceinline__ R rclamp(R x, R lo, R hi) {
+  if constexpr (sizeof(R) == 4)
+    return __builtin_amdgcn_fmed3f(x, lo, hi);
+  else
+    return rmin(rmax(x, lo), hi);
+}
 
 // ---------------------------------------------------------------------------
 // Reciprocal, quotient and square root by Newton's iteration from the
@@ -115,8 +124,8 @@ template <class R, bool FMA = true>
 __device__ __forceinline__ void ppm_limit(R qm1, R q0, R qp1, R fl, R fr, R& aL, R& aR) {
   const R lo = rmin(qm1, rmin(q0, qp1));
   const R hi = rmax(qm1, rmax(q0, qp1));
-  fl = rmin(rmax(fl, lo), hi);
-  fr = rmin(rmax(fr, lo), hi);
+  fl = rclamp(fl, lo, hi);
+  fr = rclamp(fr, lo, hi);
   const R dl = q0 - qm1, dr = qp1 - q0, dc = qp1 - qm1;
   const R h = mc_half_slope(dl, dr, dc);
   const bool ext = (fr - q0) * (q0 - fl) <= R(0);
