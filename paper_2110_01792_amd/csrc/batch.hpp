@@ -50,7 +50,7 @@ __global__ void zero_counters_kernel(int* c, int n) {
 }
 
 template <class S, class R, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT) void batch_flatten_kernel(const BatchBox<S, R>* __restrict__ boxes,
+__global__ __launch_bounds__(NT, sizeof(S) == 4 ? NT / 128 : NT / 256) void batch_flatten_kernel(const BatchBox<S, R>* __restrict__ boxes,
                                                                const WorkItem* __restrict__ items, int nitems,
                                                                int* counter, int stage) {
   __shared__ FlatSmem<R, TX, TY> sm;

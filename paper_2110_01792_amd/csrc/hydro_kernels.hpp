@@ -303,7 +303,9 @@ __device__ __forceinline__ void flatten_tile(const FlatArgs<S, R>& a, int tbx, i
 constexpr int FTX = 32, FTY = 30, FNT = 1024;
 
 template <class S, class R>
-__global__ __launch_bounds__(FNT) void flatten_kernel(FlatArgs<S, R> a, int gx, int gy) {
+// FP32: held to 64 VGPRs (8 waves per SIMD: two 1024-thread blocks per CU,
+// the whole grid resident at 256^3) to hide the z-march's load latency.
+__global__ __launch_bounds__(FNT, sizeof(S) == 4 ? 8 : 4) void flatten_kernel(FlatArgs<S, R> a, int gx, int gy) {
   __shared__ FlatSmem<R, FTX, FTY> sm;
   const TileId tl = tile_of_block(gx, gy);
   flatten_tile<S, R, FTX, FTY, FNT>(a, tl.bx, tl.by, tl.bz, sm);
@@ -872,6 +874,32 @@ __host__ __device__ __forceinline__ int64_t ghost_count(const DevBox& b) {
   return 2 * b.ng * (NY * NX + (int64_t)b.n2 * NX + (int64_t)b.n2 * b.n1);
 }
 
+// The same in 32-bit arithmetic, for boxes with fewer than 2^31 ghost cells
+// (64-bit division is a long instruction sequence on the GPU).
+__device__ __forceinline__ void ghost_cell32(const DevBox& b, uint32_t c, int& i, int& j, int& k) {
+  const int ng = b.ng;
+  const uint32_t NX = b.n0 + 2 * ng, NY = b.n1 + 2 * ng, G = 2 * ng;
+  const uint32_t nz_slab = G * NY * NX, ny_slab = G * (uint32_t)b.n2 * NX;
+  if (c < nz_slab) {
+    const uint32_t q = c / NX, kk = q / NY;
+    i = (int)(c - q * NX) - ng;
+    j = (int)(q - kk * NY) - ng;
+    k = (int)kk < ng ? (int)kk - ng : b.n2 + ((int)kk - ng);
+  } else if (c < nz_slab + ny_slab) {
+    const uint32_t r = c - nz_slab, q = r / NX, kq = q / G;
+    i = (int)(r - q * NX) - ng;
+    const int jj = (int)(q - kq * G);
+    k = (int)kq;
+    j = jj < ng ? jj - ng : b.n1 + (jj - ng);
+  } else {
+    const uint32_t r = c - nz_slab - ny_slab, q = r / G, kq = q / (uint32_t)b.n1;
+    const int ii = (int)(r - q * G);
+    j = (int)(q - kq * (uint32_t)b.n1);
+    k = (int)kq;
+    i = ii < ng ? ii - ng : b.n0 + (ii - ng);
+  }
+}
+
 __device__ __forceinline__ void ghost_cell(const DevBox& b, int64_t c, int& i, int& j, int& k) {
   const int ng = b.ng;
   const int NX = b.n0 + 2 * ng, NY = b.n1 + 2 * ng;
@@ -929,9 +957,13 @@ template <class S>
 __device__ __forceinline__ void ghost_body(S* __restrict__ U, const DevBox& b, const GhostBC& bc, int nvar) {
   const int64_t total = ghost_count(b);
   const bool ff = bc.any_ff && nvar == 4;  // radiation flux filled on its own
+  const bool small = total < ((int64_t)1 << 31);
   for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < total; c += (int64_t)gridDim.x * 256) {
     int i, j, k;
-    ghost_cell(b, c, i, j, k);
+    if (small)
+      ghost_cell32(b, (uint32_t)c, i, j, k);
+    else
+      ghost_cell(b, c, i, j, k);
     const int64_t dst = cell(b, i, j, k);
     int64_t src;
     if (ghost_src(b, bc, false, i, j, k, src))
@@ -952,9 +984,13 @@ template <class S>
 __global__ __launch_bounds__(256) void ghost_copy_kernel(S* __restrict__ dst, const S* __restrict__ src, DevBox b,
                                                          int nvar) {
   const int64_t total = ghost_count(b);
+  const bool small = total < ((int64_t)1 << 31);
   for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < total; c += (int64_t)gridDim.x * 256) {
     int i, j, k;
-    ghost_cell(b, c, i, j, k);
+    if (small)
+      ghost_cell32(b, (uint32_t)c, i, j, k);
+    else
+      ghost_cell(b, c, i, j, k);
     const int64_t o = cell(b, i, j, k);
     for (int v = 0; v < nvar; ++v) dst[o + v * b.vs] = src[o + v * b.vs];
   }
