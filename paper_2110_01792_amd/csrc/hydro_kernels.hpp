@@ -302,9 +302,9 @@ __device__ __forceinline__ void flatten_tile(const FlatArgs<S, R>& a, int tbx, i
 // halo ring), and the halo ring per cell is half that of a 16 x 14 tile.
 constexpr int FTX = 32, FTY = 30, FNT = 1024;
 
-template <class S, class R>
 // FP32: held to 64 VGPRs (8 waves per SIMD: two 1024-thread blocks per CU,
 // the whole grid resident at 256^3) to hide the z-march's load latency.
+template <class S, class R>
 __global__ __launch_bounds__(FNT, sizeof(S) == 4 ? 8 : 4) void flatten_kernel(FlatArgs<S, R> a, int gx, int gy) {
   __shared__ FlatSmem<R, FTX, FTY> sm;
   const TileId tl = tile_of_block(gx, gy);
