@@ -138,7 +138,7 @@ __device__ __forceinline__ RadStageArgs<S, R> batch_rad_args(const BatchBox<S, R
 }
 
 template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE>
-__global__ __launch_bounds__(NT, sizeof(S) == 4 ? 3 : 2) void batch_rad_kernel(const BatchBox<S, R>* __restrict__ boxes,
+__global__ __launch_bounds__(NT, sizeof(S) == 4 ? (STAGE == 1 ? 4 : 3) : 2) void batch_rad_kernel(const BatchBox<S, R>* __restrict__ boxes,
                                                               const WorkItem* __restrict__ items, int nitems,
                                                               int* counter, RadParamsDev p, const double* dt_ptr,
                                                               const int32_t* nsub_ptr, int sub, uint32_t* err,

@@ -643,7 +643,7 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
 }
 
 template <class S, class R, int STAGE>
-__global__ __launch_bounds__(SNT, sizeof(S) == 4 ? 3 : 2) void rad_stage_kernel(RadStageArgs<S, R> a) {
+__global__ __launch_bounds__(SNT, sizeof(S) == 4 ? (STAGE == 1 ? 4 : 3) : 2) void rad_stage_kernel(RadStageArgs<S, R> a) {
   const int N = a.nsub_ptr ? *a.nsub_ptr : a.nsub_val;
   if (a.sub >= N) return;  // block-uniform: the whole grid skips unused substeps
   __shared__ RadSmem<R, STX, STY, true> sm;
