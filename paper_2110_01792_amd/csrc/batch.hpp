@@ -133,6 +133,7 @@ __device__ __forceinline__ RadStageArgs<S, R> batch_rad_args(const BatchBox<S, R
   a.vfl = bb.vf[STAGE - 1];
   a.vfl_clear = bb.vf[2 - STAGE];
   a.per = 0;
+  a.wrap = 0;
   a.nthick = nthick;
   return a;
 }

@@ -860,6 +860,10 @@ struct GhostBC {
   int any_ff;  // some face is of kind 3
 };
 
+// Periodic image of index i on an axis of n >= 4 cells, for i within 4
+// cells of the axis (the reach of the stages' halos).
+__device__ __forceinline__ int wrap_near(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
 __device__ __forceinline__ int map_index(int i, int n, int lo, int hi) {
   if (i < 0) return lo == 0 ? ((i % n) + n) % n : (lo == 1 ? 0 : i);
   if (i >= n) return hi == 0 ? i % n : (hi == 1 ? n - 1 : i);
