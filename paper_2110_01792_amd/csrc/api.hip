@@ -285,6 +285,24 @@ int grid_for(int64_t n, int per_block, int cap) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, cap));
 }
 
+// Face code of the ghost images the stage kernels can read instead of ghost
+// cells (ghost_image: two bits per axis, x lowest, a set bit an outflow face),
+// or -1 when a face holds fixed data or an extent is below 4 cells.
+int image_code(const HostBox& hb) {
+  const int n[3] = {hb.d.n0, hb.d.n1, hb.d.n2};
+  int code = 0;
+  for (int q = 0; q < 3; ++q) {
+    if (n[q] < 4) return -1;
+    for (int t = 0; t < 2; ++t) {
+      if (hb.bc[q][t] == QK_BC_OUTFLOW)
+        code |= 1 << (2 * q + t);
+      else if (hb.bc[q][t] != QK_BC_PERIODIC)
+        return -1;
+    }
+  }
+  return code;
+}
+
 template <class S>
 void launch_ghosts(const HostBox& hb, S* U, int nvar, hipStream_t s) {
   const DevBox& d = hb.d;
@@ -360,11 +378,14 @@ Launch plan(int n0, int n1, int n2, int tx, int ty, int resident, int zc_target 
   return L;
 }
 
+// img: -1, or the face code under which the kernels read ghost images (see
+// image_code) instead of ghost cells.
 template <class S, class R>
-void launch_flatten(const HostBox& hb, const S* U, R* chi, double gamma, hipStream_t s) {
+void launch_flatten(const HostBox& hb, const S* U, R* chi, double gamma, hipStream_t s, int img = -1) {
   const DevBox& d = hb.d;
   static const int res = resident_grid(flatten_kernel<S, R>, FNT);
-  Launch L = plan(d.n0 + 2, d.n1 + 2, d.n2 + 2, FTX, FTY, res);
+  static const int res_i = resident_grid(flatten_kernel<S, R, true>, FNT);
+  Launch L = plan(d.n0 + 2, d.n1 + 2, d.n2 + 2, FTX, FTY, img >= 0 ? res_i : res);
   FlatArgs<S, R> a;
   a.U = U;
   a.Ugh = nullptr;
@@ -372,16 +393,21 @@ void launch_flatten(const HostBox& hb, const S* U, R* chi, double gamma, hipStre
   a.b = d;
   a.gm1 = gamma - 1.0;
   a.zc = L.zc;
-  hipLaunchKernelGGL((flatten_kernel<S, R>), dim3(L.gx * L.gy * L.gz), dim3(FNT), 0, s, a, L.gx, L.gy);
+  a.img = img;
+  if (img >= 0)
+    hipLaunchKernelGGL((flatten_kernel<S, R, true>), dim3(L.gx * L.gy * L.gz), dim3(FNT), 0, s, a, L.gx, L.gy);
+  else
+    hipLaunchKernelGGL((flatten_kernel<S, R>), dim3(L.gx * L.gy * L.gz), dim3(FNT), 0, s, a, L.gx, L.gy);
 }
 
 template <class S, class R, int STAGE>
 void launch_stage(const HostBox& hb, const S* Uin, const S* Un, S* Uout, const R* chi, double gamma,
                   const double* dt_ptr, double dt_val, unsigned long long* smax, uint32_t* err, int recon,
-                  hipStream_t s, const RegRec* rec = nullptr) {
+                  hipStream_t s, const RegRec* rec = nullptr, int img = -1) {
   const DevBox& d = hb.d;
   static const int res = resident_grid(stage_kernel<S, R, STAGE>, SNT);
-  Launch L = plan(d.n0, d.n1, d.n2, STX, STY, res, kStageChunkPlanes);
+  static const int res_i = resident_grid(stage_kernel<S, R, STAGE, true>, SNT);
+  Launch L = plan(d.n0, d.n1, d.n2, STX, STY, img >= 0 ? res_i : res, kStageChunkPlanes);
   StageArgs<S, R> a;
   a.Uin = Uin;
   a.Ugh = nullptr;
@@ -404,7 +430,11 @@ void launch_stage(const HostBox& hb, const S* Uin, const S* Un, S* Uout, const R
     a.rhi[q] = rec ? rec->hi[q] : 0;
   }
   a.rw = rec ? rec->w : 0.0;
-  hipLaunchKernelGGL((stage_kernel<S, R, STAGE>), dim3(L.gx * L.gy * L.gz), dim3(SNT), 0, s, a);
+  a.img = img;
+  if (img >= 0)
+    hipLaunchKernelGGL((stage_kernel<S, R, STAGE, true>), dim3(L.gx * L.gy * L.gz), dim3(SNT), 0, s, a);
+  else
+    hipLaunchKernelGGL((stage_kernel<S, R, STAGE>), dim3(L.gx * L.gy * L.gz), dim3(SNT), 0, s, a);
   if (rec) {
     const int64_t nf = region_face_count(rec->lo, rec->hi);
     hipLaunchKernelGGL((region_flux_kernel<S, R>), dim3(grid_for(nf, 256, 4096)), dim3(256), 0, s, a);
@@ -455,15 +485,21 @@ qk_status hydro_step_core(qk_ctx* ctx, const HostBox& hb, S* U, S* U1, R* chi, c
   tb(QK_K_HYDRO_STAGE);
   launch_stage<S, R, 1>(hb, U, U, U1, chi, hp->gamma, dtp, dtv, nullptr, &ctx->sc->err, hp->reconstruction, s, rec);
   te(QK_K_HYDRO_STAGE);
-  tb(QK_K_GHOST);
-  launch_ghosts<S>(hb, U1, 5, s);
-  te(QK_K_GHOST);
+  // A box whose faces are all periodic or outflow (and no flux register)
+  // leaves the ghosts of the stage buffer unfilled: the second stage and its
+  // flattening pass read a cell outside the box at the cell the fill copies.
+  const int img = rec ? -1 : image_code(hb);
+  if (img < 0) {
+    tb(QK_K_GHOST);
+    launch_ghosts<S>(hb, U1, 5, s);
+    te(QK_K_GHOST);
+  }
   tb(QK_K_FLATTEN);
-  launch_flatten<S, R>(hb, U1, chi, hp->gamma, s);
+  launch_flatten<S, R>(hb, U1, chi, hp->gamma, s, img);
   te(QK_K_FLATTEN);
   tb(QK_K_HYDRO_STAGE);
   launch_stage<S, R, 2>(hb, U1, U, U, chi, hp->gamma, dtp, dtv, dt_next ? &ctx->sc->smax_b : nullptr,
-                        &ctx->sc->err, hp->reconstruction, s, rec);
+                        &ctx->sc->err, hp->reconstruction, s, rec, img);
   te(QK_K_HYDRO_STAGE);
   tb(QK_K_GHOST);
   launch_ghosts<S>(hb, U, 5, s);

@@ -67,6 +67,7 @@ __global__ __launch_bounds__(NT, sizeof(S) == 4 ? NT / 128 : NT / 256) void batc
     a.b = bb.b;
     a.gm1 = bb.gamma - 1.0;
     a.zc = bb.zc_flat;
+    a.img = -1;
     flatten_tile<S, R, TX, TY, NT>(a, w.bx, w.by, w.bz, sm);
   }
 }
@@ -99,6 +100,7 @@ __global__ __launch_bounds__(NT) void batch_stage_kernel(const BatchBox<S, R>* _
     a.err = err;
     a.recon = bb.recon;
     a.reg = nullptr;
+    a.img = -1;
     stage_tile<S, R, TX, TY, NT, SPLIT, STAGE>(a, w.bx, w.by, w.bz, sm, bad);
     __syncthreads();
   }
@@ -133,7 +135,7 @@ __device__ __forceinline__ RadStageArgs<S, R> batch_rad_args(const BatchBox<S, R
   a.vfl = bb.vf[STAGE - 1];
   a.vfl_clear = bb.vf[2 - STAGE];
   a.per = 0;
-  a.wrap = 0;
+  a.img = -1;
   a.nthick = nthick;
   return a;
 }

@@ -39,6 +39,8 @@ struct StageArgs {
   double* reg;           // region_flux_kernel: flux register over the faces bounding
   int rlo[3], rhi[3];    //   region [rlo, rhi) (the stage kernel ignores these)
   double rw;             //   register weight: each face adds rw * dt/2 * F
+  int img;               // IMG kernels: face code of the ghost images (ghost_image; two
+                         // bits per axis, x lowest)
 };
 
 // Flux-register slot of variable v (of nv) on face `side` (0 low, 1 high) of
@@ -116,6 +118,7 @@ struct FlatArgs {
   DevBox b;
   double gm1;
   int zc;
+  int img;       // IMG kernels: face code of the ghost images (see StageArgs)
 };
 
 template <class R, int TX, int TY>
@@ -151,8 +154,11 @@ __device__ __forceinline__ void load_halo(const HaloCell<S>& h, const S* src, co
 // One tile of columns (tile indices over the grown range [-1, n]).  The
 // tile's own cells come from each thread's z window; the 3-cell halo ring of
 // each plane is prefetched one plane ahead into registers.  NT threads
-// (NT >= TX*TY); thread t owns column (t % TX, t / TX).
-template <class S, class R, int TX, int TY, int NT>
+// (NT >= TX*TY); thread t owns column (t % TX, t / TX).  IMG: every face of
+// the box is periodic or outflow (each extent >= 4) and its ghost cells are
+// not filled; a cell outside is read at the cell the fill would copy
+// (ghost_image with the face code a.img).
+template <class S, class R, int TX, int TY, int NT, bool IMG = false>
 __device__ __forceinline__ void flatten_tile(const FlatArgs<S, R>& a, int tbx, int tby, int tbz,
                                              FlatSmem<R, TX, TY>& sm) {
   static_assert(NT >= TX * TY, "one thread per column");
@@ -187,9 +193,13 @@ __device__ __forceinline__ void flatten_tile(const FlatArgs<S, R>& a, int tbx, i
     }
     hc[m].kind = kind;
     hc[m].src = src_at(a.U, a.Ugh, b, xs + xx, ys + yy, 0);
-    hc[m].off = cell(b, xs + xx, ys + yy, 0);
+    hc[m].off = IMG ? cell(b, ghost_image(xs + xx, b.n0, a.img & 3), ghost_image(ys + yy, b.n1, (a.img >> 2) & 3), 0)
+                    : cell(b, xs + xx, ys + yy, 0);
     hc[m].lds = (yy + 3) * (TX + 6) + (xx + 3);
   }
+  // own column and plane index as read (ghost images under IMG)
+  const int ir = IMG ? ghost_image(i, b.n0, a.img & 3) : i, jr = IMG ? ghost_image(j, b.n1, (a.img >> 2) & 3) : j;
+  auto zimg = [&](int kk) { return IMG ? ghost_image(kk, b.n2, (a.img >> 4) & 3) : kk; };
   // planes -1 and n of the grown range lie outside the interior in z
   auto hsrc = [&](const HaloCell<S>& h, int kk) {
     return (a.Ugh && (unsigned)kk >= (unsigned)b.n2) ? a.Ugh : h.src;
@@ -213,7 +223,7 @@ __device__ __forceinline__ void flatten_tile(const FlatArgs<S, R>& a, int tbx, i
     for (int s = 0; s < 6; ++s) {
       const int kk = zs - 3 + s;
       double q[5];
-      load_cons(src_at(a.U, a.Ugh, b, i, j, kk), vs, cell(b, i, j, kk), q);
+      load_cons(src_at(a.U, a.Ugh, b, i, j, kk), vs, cell(b, ir, jr, zimg(kk)), q);
       R ux, uy;
       prim(q, P[s + 1], ux, uy, uz[s + 1]);
       if (s >= 3) {
@@ -223,10 +233,11 @@ __device__ __forceinline__ void flatten_tile(const FlatArgs<S, R>& a, int tbx, i
     }
     cz[1] = chi_tilde<R>(P[1], P[2], P[4], P[5], uz[2], uz[4]);
     cz[2] = chi_tilde<R>(P[2], P[3], P[5], P[6], uz[3], uz[5]);
-    load_cons(src_at(a.U, a.Ugh, b, i, j, zs + 3), vs, cell(b, i, j, zs + 3), cq);
+    load_cons(src_at(a.U, a.Ugh, b, i, j, zs + 3), vs, cell(b, ir, jr, zimg(zs + 3)), cq);
   }
 #pragma unroll
-  for (int m = 0; m < HPT; ++m) load_halo<5>(hc[m], hsrc(hc[m], zs), (const R*)nullptr, (int64_t)zs * pz, vs, hq[m]);
+  for (int m = 0; m < HPT; ++m)
+    load_halo<5>(hc[m], hsrc(hc[m], zs), (const R*)nullptr, (int64_t)zimg(zs) * pz, vs, hq[m]);
 
   for (int k = zs; k < ze; ++k) {
     if (act) {
@@ -260,10 +271,10 @@ __device__ __forceinline__ void flatten_tile(const FlatArgs<S, R>& a, int tbx, i
       }
     }
     if (k + 1 < ze) {
-      if (act) load_cons(src_at(a.U, a.Ugh, b, i, j, k + 4), vs, cell(b, i, j, k + 4), cq);
+      if (act) load_cons(src_at(a.U, a.Ugh, b, i, j, k + 4), vs, cell(b, ir, jr, zimg(k + 4)), cq);
 #pragma unroll
       for (int m = 0; m < HPT; ++m)
-        load_halo<5>(hc[m], hsrc(hc[m], k + 1), (const R*)nullptr, (int64_t)(k + 1) * pz, vs, hq[m]);
+        load_halo<5>(hc[m], hsrc(hc[m], k + 1), (const R*)nullptr, (int64_t)zimg(k + 1) * pz, vs, hq[m]);
     }
     __syncthreads();
     for (int it = t; it < (TX + 2) * TY; it += NT) {
@@ -304,11 +315,11 @@ constexpr int FTX = 32, FTY = 30, FNT = 1024;
 
 // FP32: held to 64 VGPRs (8 waves per SIMD: two 1024-thread blocks per CU,
 // the whole grid resident at 256^3) to hide the z-march's load latency.
-template <class S, class R>
+template <class S, class R, bool IMG = false>
 __global__ __launch_bounds__(FNT, sizeof(S) == 4 ? 8 : 4) void flatten_kernel(FlatArgs<S, R> a, int gx, int gy) {
   __shared__ FlatSmem<R, FTX, FTY> sm;
   const TileId tl = tile_of_block(gx, gy);
-  flatten_tile<S, R, FTX, FTY, FNT>(a, tl.bx, tl.by, tl.bz, sm);
+  flatten_tile<S, R, FTX, FTY, FNT, IMG>(a, tl.bx, tl.by, tl.bz, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -363,7 +374,7 @@ struct HydroSmem {
 // One tile of columns of one box: returns the thread's max(|v| + c_s) of the
 // new state (stage 2 with a.smax set), sets `bad` on a non-positive state.
 // NT threads (NT >= TX*TY); thread t owns column (t % TX, t / TX).
-template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE>
+template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE, bool IMG = false>
 __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, int tby, int tbz,
                                              HydroSmem<R, TX, TY, SPLIT>& sm, bool& bad_out) {
   using SM = HydroSmem<R, TX, TY, SPLIT>;
@@ -426,9 +437,14 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
     lds = kind == 2 ? (yy + 1) * (TX + 2) + (xx + 1) : (yy + 3) * (TX + 6) + (xx + 3);
     hc[m].kind = kind;
     hc[m].src = src_at(Uin, a.Ugh, b, x0 + xx, y0 + yy, z0);
-    hc[m].off = cell(b, x0 + xx, y0 + yy, 0);
+    // IMG: the state ring at its ghost images; the flattening ring (kind 2)
+    // where it lies, since the flattening pass covers the grown range
+    hc[m].off = (IMG && kind == 1)
+                    ? cell(b, ghost_image(x0 + xx, b.n0, a.img & 3), ghost_image(y0 + yy, b.n1, (a.img >> 2) & 3), 0)
+                    : cell(b, x0 + xx, y0 + yy, 0);
     hc[m].lds = lds;
   }
+  auto zimg = [&](int kk) { return IMG ? ghost_image(kk, b.n2, (a.img >> 4) & 3) : kk; };
 
   R w[5][5];  // own column primitives: [var][plane slot], slot s = plane m-2+s
   R aRz[5], Fz[5];
@@ -445,7 +461,7 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
   };
   auto load_w = [&](int kk, int slot) {
     double q[5];
-    load_cons(src_at(Uin, a.Ugh, b, i, j, kk), vs, cell(b, i, j, kk), q);
+    load_cons(src_at(Uin, a.Ugh, b, i, j, kk), vs, cell(b, i, j, zimg(kk)), q);
     prim_w(q, slot);
   };
   auto shift_w = [&]() {
@@ -497,7 +513,7 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
     hllc<R>(rprev, l, g, Fz);
 #pragma unroll
     for (int v = 0; v < 5; ++v) aRz[v] = rcur[v];
-    load_cons(src_at(Uin, a.Ugh, b, i, j, z0 + 3), vs, cell(b, i, j, z0 + 3), cq);
+    load_cons(src_at(Uin, a.Ugh, b, i, j, z0 + 3), vs, cell(b, i, j, zimg(z0 + 3)), cq);
   }
 #pragma unroll
   for (int m = 0; m < HPT; ++m) load_halo<5>(hc[m], hc[m].src, chi, (int64_t)z0 * pz, vs, hq[m]);
@@ -531,7 +547,7 @@ __device__ __forceinline__ double stage_tile(const StageArgs<S, R>& a, int tbx, 
       chn = chi[o + pz];
       load_cons(Uin, vs, o, uo);
       if (STAGE == 2) load_cons(a.Un, vs, o, un);
-      if (k + 1 < z1) load_cons(src_at(Uin, a.Ugh, b, i, j, k + 4), vs, o + 4 * pz, cq);
+      if (k + 1 < z1) load_cons(src_at(Uin, a.Ugh, b, i, j, k + 4), vs, cell(b, i, j, zimg(k + 4)), cq);
     }
     if (k + 1 < z1) {
 #pragma unroll
@@ -790,12 +806,12 @@ __global__ __launch_bounds__(256) void region_flux_kernel(StageArgs<S, R> a) {
 // item per thread.
 constexpr int STX = 16, STY = 14, SNT = 256;
 
-template <class S, class R, int STAGE>
+template <class S, class R, int STAGE, bool IMG = false>
 __global__ __launch_bounds__(SNT) void stage_kernel(StageArgs<S, R> a) {
   __shared__ HydroSmem<R, STX, STY, true> sm;
   const TileId tl = tile_of_block(a.gx, a.gy);
   bool bad = false;
-  const double smax = stage_tile<S, R, STX, STY, SNT, true, STAGE>(a, tl.bx, tl.by, tl.bz, sm, bad);
+  const double smax = stage_tile<S, R, STX, STY, SNT, true, STAGE, IMG>(a, tl.bx, tl.by, tl.bz, sm, bad);
   if (bad) atomicOr(a.err, ERR_NEG);
   if (STAGE == 2 && a.smax) block_max_to<SNT>(smax, a.smax);
 }
@@ -859,10 +875,6 @@ struct GhostBC {
   int lo[3], hi[3];
   int any_ff;  // some face is of kind 3
 };
-
-// Periodic image of index i on an axis of n >= 4 cells, for i within 4
-// cells of the axis (the reach of the stages' halos).
-__device__ __forceinline__ int wrap_near(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 __device__ __forceinline__ int map_index(int i, int n, int lo, int hi) {
   if (i < 0) return lo == 0 ? ((i % n) + n) % n : (lo == 1 ? 0 : i);

@@ -24,6 +24,14 @@ __device__ __forceinline__ int64_t cell(const DevBox& b, int i, int j, int k) {
   return (int64_t)(k + b.ng) * b.pz + (int64_t)(j + b.ng) * b.py + (i + b.ng);
 }
 
+// The cell whose value a ghost at index i holds after the ghost fill, on an
+// axis of n >= 4 cells whose faces are periodic or outflow, for i within 4
+// cells of the axis (the reach of the stages' halos).  code bit 0: the low
+// face is outflow (else periodic); bit 1: the high face.
+__device__ __forceinline__ int ghost_image(int i, int n, int code) {
+  return i < 0 ? ((code & 1) ? 0 : i + n) : (i >= n ? ((code & 2) ? n - 1 : i - n) : i);
+}
+
 template <class R> __device__ __forceinline__ R rmin(R a, R b) { return fmin(a, b); }
 template <class R> __device__ __forceinline__ R rmax(R a, R b) { return fmax(a, b); }
 // min(max(x, lo), hi) for lo <= hi; in FP32 one median-of-three instruction

@@ -47,10 +47,10 @@ struct RadStageArgs {
   uint8_t* vfl;            // set to 1 by this stage at cells that violate |F| <= c E_r
   uint8_t* vfl_clear;      // flags of the other stage, cleared by this stage's fix-up
   int per;                 // bit d set: axis d is periodic (a face there joins both ends)
-  int wrap;                // every face periodic and the stage input's ghost cells not kept:
-                           // a cell outside the box is read at its periodic image (the
-                           // stage kernel takes this as its WRAP template argument; every
-                           // extent is then at least 4)
+  int img;                 // -1, or: every face periodic or outflow, every extent >= 4, and
+                           // the stage input's ghost cells not kept: a cell outside the box
+                           // is read at the cell the fill would copy (ghost_image with this
+                           // face code; the stage kernel then runs as its IMG instance)
   const uint32_t* nthick;  // number of thick cells of the step (NULL: not counted).  When it is
                            // 0 no face has tau > 1, the factor is 1 everywhere, and the stage
                            // skips the density halo and the optical depths altogether
@@ -248,7 +248,7 @@ struct RadSmem {
 // One tile of columns of one box for substep `a.sub` (the caller has checked
 // that the substep is active).  Returns the largest exchange iteration count.
 // NT threads (NT >= TX*TY); thread t owns column (t % TX, t / TX).
-template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE, bool WRAP = false>
+template <class S, class R, int TX, int TY, int NT, bool SPLIT, int STAGE, bool IMG = false>
 __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tbx, int tby, int tbz, int N,
                                              RadSmem<R, TX, TY, SPLIT>& sm, bool& bad_out, bool& nfail_out) {
   using SM = RadSmem<R, TX, TY, SPLIT>;
@@ -315,7 +315,11 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
     }
     hc[m].kind = kind;
     hc[m].src = src_at(Uin, a.Ugh, b, x0 + xx, y0 + yy, z0);
-    hc[m].off = WRAP ? cell(b, wrap_near(x0 + xx, b.n0), wrap_near(y0 + yy, b.n1), 0) : cell(b, x0 + xx, y0 + yy, 0);
+    // IMG: the radiation ring at its ghost images; the density ring (kind 2)
+    // where it lies (the gas ghosts are filled)
+    hc[m].off = (IMG && kind == 1)
+                    ? cell(b, ghost_image(x0 + xx, b.n0, a.img & 3), ghost_image(y0 + yy, b.n1, (a.img >> 2) & 3), 0)
+                    : cell(b, x0 + xx, y0 + yy, 0);
     hc[m].lds = kind == 2 ? (yy + 1) * (TX + 2) + (xx + 1) : (yy + 3) * (TX + 6) + (xx + 3);
   }
 
@@ -342,7 +346,7 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
 #pragma unroll
     for (int v = 0; v < 4; ++v) q[v] = double(U[o + v * vs]);
   };
-  auto zimg = [&](int kk) { return WRAP ? wrap_near(kk, b.n2) : kk; };
+  auto zimg = [&](int kk) { return IMG ? ghost_image(kk, b.n2, (a.img >> 4) & 3) : kk; };
   auto load_w = [&](int kk, int slot) {
     double q[4];
     load4(src_at(Uin, a.Ugh, b, i, j, kk), cell(b, i, j, zimg(kk)), q);
@@ -647,14 +651,14 @@ __device__ __forceinline__ uint32_t rad_tile(const RadStageArgs<S, R>& a, int tb
   return itmax;
 }
 
-template <class S, class R, int STAGE, bool WRAP = false>
+template <class S, class R, int STAGE, bool IMG = false>
 __global__ __launch_bounds__(SNT, sizeof(S) == 4 ? (STAGE == 1 ? 4 : 3) : 2) void rad_stage_kernel(RadStageArgs<S, R> a) {
   const int N = a.nsub_ptr ? *a.nsub_ptr : a.nsub_val;
   if (a.sub >= N) return;  // block-uniform: the whole grid skips unused substeps
   __shared__ RadSmem<R, STX, STY, true> sm;
   const TileId tl = tile_of_block(a.gx, a.gy);
   bool bad = false, nfail = false;
-  const uint32_t itmax = rad_tile<S, R, STX, STY, SNT, true, STAGE, WRAP>(a, tl.bx, tl.by, tl.bz, N, sm, bad, nfail);
+  const uint32_t itmax = rad_tile<S, R, STX, STY, SNT, true, STAGE, IMG>(a, tl.bx, tl.by, tl.bz, N, sm, bad, nfail);
   if (bad) atomicOr(a.err, ERR_NEG);
   if (nfail) atomicOr(a.err, ERR_NEWTON);
   if (STAGE == 2) block_umax_to<SNT>(itmax, a.iter_max);
@@ -677,8 +681,9 @@ __device__ __forceinline__ void rad_flux_at(const RadStageArgs<S, R>& a, int d, 
   for (int s = 0; s < 6; ++s) {
     const int ii = i + ei * (s - 3), jj = j + ej * (s - 3), kk = k + ek * (s - 3);
     const S* src = src_at(a.Uin, a.Ugh, b, ii, jj, kk);
-    const int64_t o = a.wrap ? cell(b, map_index(ii, b.n0, 0, 0), map_index(jj, b.n1, 0, 0), map_index(kk, b.n2, 0, 0))
-                             : cell(b, ii, jj, kk);
+    const int64_t o = a.img >= 0 ? cell(b, ghost_image(ii, b.n0, a.img & 3), ghost_image(jj, b.n1, (a.img >> 2) & 3),
+                                        ghost_image(kk, b.n2, (a.img >> 4) & 3))
+                                 : cell(b, ii, jj, kk);
     const R Er = R(double(src[o]));
     const R inv = rcp_nz(c * Er);  // E_r > 0
     Q[s][0] = Er;

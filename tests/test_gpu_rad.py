@@ -331,6 +331,21 @@ def test_causality_rule_matches_oracle(ctx, n, nsteps):
     assert np.max(np.abs(nr[0] - orr[0])) > 1e-6 * np.max(np.abs(orr[0]))
 
 
+def test_causality_rule_periodic_box(ctx):
+    """The same slab in a box periodic on every face: the radiation stages
+    skip the ghost fills between stages and read cells outside the box at
+    their periodic images, the fix-up included; the beam leaving at x = 1
+    re-enters at x = 0, so thick and streaming cells also meet across the
+    periodic boundary."""
+    b0, Ug, Ur, p = inputs.rad_thick_streaming(n=(24, 12, 8))
+    b = inputs.Box(b0.n, b0.ng, b0.dx, ((inputs.PERIODIC, inputs.PERIODIC),) * 3)
+    gg, gr, st = gpu_rhd(ctx, b, Ug, Ur, p, 2)
+    assert st == qb.QK_OK
+    og, orr, causal = _oracle_rhd_counting(b, Ug, Ur, p, 2)
+    assert causal > 0
+    check_pair((gg, gr), (og, orr), b, "causality rule, periodic box")
+
+
 def test_causality_rule_mixed_precision_stays_causal_and_positive(ctx):
     """The FP32 path on the thick slab: the rule keeps it positive and close
     to the FP64 oracle (normalised L1 per variable within 1e-3 on this
