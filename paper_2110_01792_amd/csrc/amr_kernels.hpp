@@ -18,9 +18,19 @@ __global__ __launch_bounds__(256) void average_down_kernel(const S* __restrict__
                                                            DevBox cb, int o0, int o1, int o2, int nvar) {
   const int m0 = fb.n0 / 2, m1 = fb.n1 / 2, m2 = fb.n2 / 2;
   const int64_t total = (int64_t)m0 * m1 * m2 * nvar;
+  const bool small = total < ((int64_t)1 << 31);  // 32-bit index arithmetic (64-bit division is long)
   for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < total; c += (int64_t)gridDim.x * 256) {
-    const int I = (int)(c % m0), J = (int)((c / m0) % m1), K = (int)((c / ((int64_t)m0 * m1)) % m2);
-    const int v = (int)(c / ((int64_t)m0 * m1 * m2));
+    int I, J, K, v;
+    if (small) {
+      const uint32_t u = (uint32_t)c, q0 = u / (uint32_t)m0, q1 = q0 / (uint32_t)m1, q2 = q1 / (uint32_t)m2;
+      I = (int)(u - q0 * (uint32_t)m0);
+      J = (int)(q0 - q1 * (uint32_t)m1);
+      K = (int)(q1 - q2 * (uint32_t)m2);
+      v = (int)q2;
+    } else {
+      I = (int)(c % m0), J = (int)((c / m0) % m1), K = (int)((c / ((int64_t)m0 * m1)) % m2);
+      v = (int)(c / ((int64_t)m0 * m1 * m2));
+    }
     const S* f = Uf + (int64_t)v * fb.vs;
     double s = 0.0;
 #pragma unroll
@@ -41,16 +51,30 @@ __global__ __launch_bounds__(256) void prolong_kernel(const S* __restrict__ U0, 
   const int NX = fb.n0 + 2 * ng, NY = fb.n1 + 2 * ng, NZ = fb.n2 + 2 * ng;
   const int64_t per_v = interior ? (int64_t)NX * NY * NZ : ghost_count(fb);
   const int64_t total = per_v * nvar;
+  const bool small = total < ((int64_t)1 << 31);  // 32-bit index arithmetic (64-bit division is long)
   for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < total; c += (int64_t)gridDim.x * 256) {
-    const int v = (int)(c / per_v);
-    const int64_t r = c - (int64_t)v * per_v;
-    int i, j, k;
-    if (interior) {
-      i = (int)(r % NX) - ng;
-      j = (int)((r / NX) % NY) - ng;
-      k = (int)(r / ((int64_t)NX * NY)) - ng;
+    int v, i, j, k;
+    if (small) {
+      const uint32_t u = (uint32_t)c, pv = (uint32_t)per_v, qv = u / pv, r = u - qv * pv;
+      v = (int)qv;
+      if (interior) {
+        const uint32_t q0 = r / (uint32_t)NX, q1 = q0 / (uint32_t)NY;
+        i = (int)(r - q0 * (uint32_t)NX) - ng;
+        j = (int)(q0 - q1 * (uint32_t)NY) - ng;
+        k = (int)q1 - ng;
+      } else {
+        ghost_cell32(fb, r, i, j, k);
+      }
     } else {
-      ghost_cell(fb, r, i, j, k);
+      v = (int)(c / per_v);
+      const int64_t r = c - (int64_t)v * per_v;
+      if (interior) {
+        i = (int)(r % NX) - ng;
+        j = (int)((r / NX) % NY) - ng;
+        k = (int)(r / ((int64_t)NX * NY)) - ng;
+      } else {
+        ghost_cell(fb, r, i, j, k);
+      }
     }
     const int P[3] = {o0 + floor_div2(i), o1 + floor_div2(j), o2 + floor_div2(k)};
     const int f[3] = {i, j, k};

@@ -828,10 +828,19 @@ __global__ __launch_bounds__(NT) void max_signal_kernel(const S* __restrict__ U,
   const double gm1 = gamma - 1.0;
   double m = 0.0;
   bool bad = false;
+  const bool small = ncell < ((int64_t)1 << 31);  // 32-bit index arithmetic (64-bit division is long)
   for (int64_t c = (int64_t)blockIdx.x * NT + threadIdx.x; c < ncell; c += (int64_t)gridDim.x * NT) {
-    const int i = (int)(c % b.n0);
-    const int j = (int)((c / b.n0) % b.n1);
-    const int k = (int)(c / ((int64_t)b.n0 * b.n1));
+    int i, j, k;
+    if (small) {
+      const uint32_t u = (uint32_t)c, q = u / (uint32_t)b.n0, kq = q / (uint32_t)b.n1;
+      i = (int)(u - q * (uint32_t)b.n0);
+      j = (int)(q - kq * (uint32_t)b.n1);
+      k = (int)kq;
+    } else {
+      i = (int)(c % b.n0);
+      j = (int)((c / b.n0) % b.n1);
+      k = (int)(c / ((int64_t)b.n0 * b.n1));
+    }
     double q[5];
     load_cons(U, b.vs, cell(b, i, j, k), q);
     m = fmax(m, signal_speed(q, gamma, gm1, bad));

@@ -825,10 +825,11 @@ __device__ __forceinline__ void thick_list_box(const DevBox& b, const S* Ug, dou
     const int64_t t = base + lane;
     bool th = false;
     int i = 0, j = 0, k = 0;
-    if (t < n) {
-      i = (int)(t % b.n0);
-      j = (int)((t / b.n0) % b.n1);
-      k = (int)(t / ((int64_t)b.n0 * b.n1));
+    if (t < n) {  // n < 2^31 (checked on the host): 32-bit index arithmetic
+      const uint32_t u = (uint32_t)t, q = u / (uint32_t)b.n0, kq = q / (uint32_t)b.n1;
+      i = (int)(u - q * (uint32_t)b.n0);
+      j = (int)(q - kq * (uint32_t)b.n1);
+      k = (int)kq;
       th = cell_is_thick<S, R>(b, Ug, R(kappa), i, j, k);
     }
     const unsigned long long m = __ballot(th);
