@@ -62,6 +62,30 @@ def test_shock_ragged_tiles(ctx, n):
     check(gpu_steps(ctx, b, U, p["gamma"], p["cfl"], 2), oracle_steps(b, U, p["gamma"], p["cfl"], 2), b)
 
 
+@pytest.mark.parametrize("bc", [inputs.PERIODIC, inputs.OUTFLOW,
+                                ((inputs.PERIODIC, inputs.PERIODIC), (inputs.OUTFLOW, inputs.OUTFLOW),
+                                 (inputs.PERIODIC, inputs.PERIODIC))], ids=["periodic", "outflow", "mixed"])
+@pytest.mark.parametrize("n", [(4, 5, 6), (4, 4, 4), (3, 9, 5)])
+def test_ghost_images_on_small_boxes(ctx, n, bc):
+    """Boxes with only periodic and outflow faces leave the stage buffer's
+    ghosts unfilled and read the cells the fill would copy; with an extent
+    of exactly 4 a periodic image of the 4-deep halo lies at the far side
+    of the box.  Extents below 4 take the ghost fill.  Smooth data with
+    velocities, 3 steps, against the oracle."""
+    b = inputs.make_box(n, bc=bc)
+    rng = np.random.default_rng(11)
+    U = np.zeros((5,) + b.shape)
+    g = b.ng
+    sl = (slice(g, g + n[2]), slice(g, g + n[1]), slice(g, g + n[0]))
+    rho = 1.0 + 0.2 * rng.uniform(size=(n[2], n[1], n[0]))
+    v = rng.uniform(-0.3, 0.3, size=(3, n[2], n[1], n[0]))
+    P = 1.0 + 0.2 * rng.uniform(size=(n[2], n[1], n[0]))
+    U[(0,) + sl] = rho
+    U[(slice(1, 4),) + sl] = rho * v
+    U[(4,) + sl] = P / (5.0 / 3.0 - 1.0) + 0.5 * rho * (v ** 2).sum(axis=0)
+    check(gpu_steps(ctx, b, U, 5.0 / 3.0, 0.3, 3), oracle_steps(b, U, 5.0 / 3.0, 0.3, 3), b, what=f"{n} {bc}")
+
+
 @pytest.mark.parametrize("n", [32, (40, 35, 27)])
 def test_plm_reconstruction(ctx, n):
     """PLM option (Section 2.2.1): smooth periodic and ragged shock boxes."""

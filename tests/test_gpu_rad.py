@@ -346,6 +346,23 @@ def test_causality_rule_periodic_box(ctx):
     check_pair((gg, gr), (og, orr), b, "causality rule, periodic box")
 
 
+@pytest.mark.parametrize("n", [(4, 5, 6), (6, 4, 4)])
+def test_rhd_ghost_images_on_small_boxes(ctx, n):
+    """The RHD workload on periodic boxes with an extent of exactly 4: the
+    radiation stages read the periodic images of a 3-deep halo and skip
+    the fills between stages; two steps against the oracle."""
+    b0, Ug0, Ur0, p = inputs.rhd_lognormal(n=max(n))
+    b = inputs.make_box(n)
+    g = b.ng
+    sl = (slice(None), slice(g, g + n[2]), slice(g, g + n[1]), slice(g, g + n[0]))
+    Ug, Ur = np.zeros((5,) + b.shape), np.zeros((4,) + b.shape)
+    Ug[sl], Ur[sl] = Ug0[sl], Ur0[sl]
+    gg, gr, st = gpu_rhd(ctx, b, Ug, Ur, p, 2)
+    assert st == qb.QK_OK
+    og, orr, _ = oracle_rhd(b, Ug, Ur, p, 2)
+    check_pair((gg, gr), (og, orr), b, f"rhd small box {n}")
+
+
 def test_causality_rule_mixed_precision_stays_causal_and_positive(ctx):
     """The FP32 path on the thick slab: the rule keeps it positive and close
     to the FP64 oracle (normalised L1 per variable within 1e-3 on this
