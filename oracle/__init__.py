@@ -10,8 +10,8 @@ A box is any object with attributes n (nx, ny, nz), ng, dx (3 floats) and
 bc ((lo, hi) per axis, 0 periodic, 1 outflow, 2 fixed, 3 fixed with a
 zero-gradient radiation flux).
 
-Functions that no independent check fixes are marked "parity unpinned" in
-their docstring (see the test files for the pins of the others).
+A function that no independent check fixes would be marked "parity
+unpinned" in its docstring; every function here has pins (tests/test_oracle_*.py).
 """
 import ctypes
 import os
