@@ -420,7 +420,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         log("bench.py runs on one GPU only: the update is measured on one GPU's 256^3 share; "
-            "multi-GPU halo exchange is not part of this build (--gpus must be 1)")
+            "the library has no multi-GPU halo exchange (--gpus must be 1)")
         sys.exit(2)
 
     import torch
