@@ -129,10 +129,6 @@ RAD_BYTES_STAGE1 = 64.0
 RAD_BYTES_STAGE2 = 168.0   # read Ur1, Ur (64) + gas (40), write Ur (32) + m, E (32)
 
 
-# with nsub_max = 10 substeps; the bench uses each run's mean substep count
-RHD_BYTES_PER_CELL_STEP = HYDRO_BYTES_PER_CELL_STEP + 10 * (RAD_BYTES_STAGE1 + RAD_BYTES_STAGE2)
-
-
 def bench_rhd(ctx, qb, inputs, torch, steps, warmup, dtype, n=256, recon=0, closure=0, source=False):
     b, Ug, Ur, p = inputs.rhd_lognormal(n=n)
     p = dict(p, recon=recon, closure=closure)
@@ -149,11 +145,16 @@ def bench_rhd(ctx, qb, inputs, torch, steps, warmup, dtype, n=256, recon=0, clos
     step = lambda: ctx.rhd_step(b, G, R, rp)
     for _ in range(warmup):
         step()
+    G0, R0 = G.clone(), R.clone()  # state at the first timed step
     ms = timed_steps(step, steps, torch)
     st = ctx.sync_status()
-    # Second pass: per-kernel HIP events, and the substep count N of every step
-    # (N = ceil(dt_h / dt_r) <= nsub_max; launches for substeps beyond N
-    # return at once and are not counted as work).
+    # Second pass over the same steps (the path is deterministic): per-kernel
+    # HIP events, and the substep count N of every step (N = ceil(dt_h / dt_r)
+    # <= nsub_max follows the hydro dt, so it changes as the flow develops;
+    # launches for substeps beyond N return at once and are not counted as work).
+    G.copy_(G0)
+    R.copy_(R0)
+    del G0, R0
     ctx.newton_iter_max()
     hp = qb.hydro_params(p["gamma"], p["cfl"], recon)
     nsub = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -176,10 +177,10 @@ def bench_rhd(ctx, qb, inputs, torch, steps, warmup, dtype, n=256, recon=0, clos
     out = {"ms_per_step": ms / steps, "cell_updates_per_s": ncell * steps / (ms * 1e-3), "status": int(st),
            "rad_stage1_ms_avg": r1_ms / nact, "rad_stage2_couple_ms_avg": r2_ms / nact,
            "hydro_stage_ms_avg": hs_ms / max(nh, 1), "launches": [n1, n2, nh], "active_substeps": nact,
-           "nsub_mean": nmean, "newton_iter_max": it,
+           "nsub_mean": nmean, "nsub_range": [min(ns), max(ns)], "newton_iter_max": it,
            "ncells": ncell, "reconstruction": "PLM" if recon == 1 else "PPM",
            "closure": ("Levermore", "Eddington", "Minerbo")[closure], "source": bool(source)}
-    # algorithmic bytes of a step with the mean substep count of the run
+    # algorithmic bytes of a step with the mean substep count of the timed steps
     rhd_bytes = HYDRO_BYTES_PER_CELL_STEP + nmean * (RAD_BYTES_STAGE1 + RAD_BYTES_STAGE2)
     out["bytes_per_cell_step"] = rhd_bytes * scale
     out["step_hbm_frac"] = rhd_bytes * scale * out["cell_updates_per_s"] / (HBM_PEAK_GBS * 1e9)

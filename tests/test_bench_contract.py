@@ -26,7 +26,9 @@ def test_counter_figures_belong_to_the_committed_kernels():
 def test_flop_and_byte_counts_per_cell():
     assert bench.HYDRO_FLOPS_PER_CELL_STAGE == 45 * 15 + 106 * 3 + 13 + 57.5 + 11
     assert bench.HYDRO_BYTES_PER_CELL_STEP == 200.0
-    assert bench.RHD_BYTES_PER_CELL_STEP == 200.0 + 10 * (64.0 + 168.0)
+    # a radiation substep: stage 1 reads and writes (E_r, F); stage 2 with the
+    # coupling also reads the stage buffer and the gas and writes m, E
+    assert (bench.RAD_BYTES_STAGE1, bench.RAD_BYTES_STAGE2) == (64.0, 168.0)
 
 
 def test_more_than_one_gpu_is_refused_without_a_device():

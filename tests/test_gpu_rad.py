@@ -99,8 +99,9 @@ def test_rhd_256_full_size(ctx):
 
 
 def test_substep_count_and_dt(ctx):
-    """Section 2.2.4 substep cap: N = 10 on the RHD workload; the dt the device
-    takes equals the oracle's."""
+    """Section 2.2.4 substep cap: N = 10 on the RHD workload's initial state
+    (the reduced speed of light is 10 times its largest sound speed); the dt
+    the device takes equals the oracle's."""
     torch = pytest.importorskip("torch")
     b, Ug, Ur, p = inputs.rhd_lognormal(n=32)
     G = dev(Ug)
